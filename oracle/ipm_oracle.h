@@ -1,0 +1,112 @@
+/*
+ * ipm_oracle.h -- plain FP64 CPU oracle of the Intrusive Polynomial Moment
+ * (IPM) hot path of Kusch, Wolters and Frank, "Intrusive acceleration
+ * strategies for uncertainty quantification for hyperbolic systems of
+ * conservation laws" (arXiv:1912.09238).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.  The
+ * product library never links, includes or calls it, and the two share no
+ * code (tables, closures, solvers and the scheme are written twice).
+ *
+ * Everything is FP64, scalar loops, one cell at a time.  OpenMP is used only
+ * to run independent cells of one step on several cores; per-cell results
+ * do not depend on the thread count.
+ *
+ * Parity pins: every function here is pinned by the "not gpu" tests against
+ * closed forms, special cases (stochastic Galerkin, deterministic finite
+ * volumes, coupled collocation at N = Q), invariants (conservation, maximum
+ * principle, dual round trip) and brute-force collocation.  The exact
+ * moment trajectories for N < Q with a non-quadratic entropy are fixed by
+ * nothing but this oracle ("parity unpinned" for that case).
+ */
+#ifndef IPM_ORACLE_H
+#define IPM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXM 4
+
+enum { ORC_BURGERS_1D = 0, ORC_EULER_1D = 1, ORC_EULER_2D = 2 };
+enum { ORC_ENT_QUADRATIC = 0, ORC_ENT_LOG_BARRIER = 1, ORC_ENT_EULER = 2 };
+enum { ORC_FLUX_LF = 0, ORC_FLUX_RUSANOV = 1 };
+enum { ORC_BC_OUTFLOW = 0, ORC_BC_PERIODIC = 1, ORC_BC_DIRICHLET = 2 };
+
+/* status bits, sticky per problem */
+enum {
+  ORC_ST_NEWTON = 1,        /* dual not converged within max_newton */
+  ORC_ST_REALIZABILITY = 2, /* ansatz outside the closure's domain */
+  ORC_ST_NONFINITE = 4,     /* NaN/Inf in gradient, wave speed or moments */
+  ORC_ST_CHOLESKY = 8,      /* non-positive pivot in the Hessian factor */
+  ORC_ST_LINESEARCH = 16    /* no admissible step after 60 halvings */
+};
+
+typedef struct {
+  int equation;          /* ORC_BURGERS_1D | ORC_EULER_1D | ORC_EULER_2D */
+  int entropy;           /* ORC_ENT_* */
+  int flux;              /* ORC_FLUX_* */
+  double gamma;          /* ratio of specific heats (Euler) */
+  double u_minus, u_plus;/* log-barrier bounds (Burgers) */
+  int p;                 /* number of uncertain dimensions */
+  int degree;            /* total degree M of the basis */
+  int quad_per_dim;      /* tensor Gauss-Legendre points per dimension */
+  int nx, ny;            /* cells (ny = 1 in 1D) */
+  double x0, x1, y0, y1; /* domain */
+  int bc[4];             /* x-, x+, y-, y+ : ORC_BC_* */
+  double cfl, t_end, tau, steady_eps;
+  int max_newton, one_shot;
+} orc_problem;
+
+typedef struct {
+  double t, dt, residual, amax;
+  long long steps, newton_iters, cell_updates;
+  int max_iters, status, done;
+} orc_info;
+
+typedef struct orc_state orc_state;
+
+/* tables */
+int orc_num_basis(int p, int degree);
+int orc_gauss_legendre(int n, double *x, double *w);
+int orc_quadrature(int p, int qpd, double *nodes /*[Q][p]*/, double *w /*[Q], sum 1*/);
+int orc_multi_indices(int p, int degree, int *idx /*[N][p]*/);
+void orc_basis_eval(int p, int degree, int Q, const double *nodes, double *Phi /*[Q][N]*/);
+
+/* closures at one node; m = 1 (scalar) or d+2 (Euler) */
+int orc_closure(int entropy, int m, double gamma, double um, double up,
+                const double *Lam, double *u, double *J /*[m][m]*/, double *sstar);
+int orc_entropy_grad(int entropy, int m, double gamma, double um, double up,
+                     const double *u, double *Lam);
+double orc_entropy(int entropy, int m, double gamma, double um, double up, const double *u);
+
+/* problem state */
+orc_state *orc_create(const orc_problem *pb, const signed char *cell_degree,
+                      const double *ic_nodal /*[cells][Q][m]*/,
+                      const double *dirichlet_nodal /*[4][Q][m] or NULL*/);
+void orc_destroy(orc_state *S);
+void orc_sizes(const orc_state *S, int *m, int *N, int *Q, int *cells);
+int orc_step(orc_state *S, int max_steps, orc_info *info);
+void orc_get_info(const orc_state *S, orc_info *info);
+void orc_get_moments(const orc_state *S, double *out /*[cells][m][N]*/);
+void orc_set_moments(orc_state *S, const double *in);
+void orc_get_dual(const orc_state *S, double *out /*[cells][m][N]*/);
+void orc_set_dual(orc_state *S, const double *in);
+void orc_get_iters(const orc_state *S, int *out /*[cells]*/);
+int orc_get_nodal(const orc_state *S, double *out /*[cells][Q][m]*/);
+void orc_tables(const orc_state *S, double *nodes, double *w, double *Phi);
+
+/* one cell's dual problem (full degree of the problem) */
+int orc_dual_cost(const orc_state *S, const double *lam, const double *uhat,
+                  double *L, double *grad /*[m][N]*/, double *H /*[mN][mN]*/);
+int orc_dual_solve(const orc_state *S, const double *uhat, double *lam, int one_shot, int *iters);
+int orc_moments_of_dual(const orc_state *S, const double *lam, double *uhat);
+
+int orc_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
