@@ -1,0 +1,187 @@
+/*
+ * ipm.h -- C ABI of libipm, an MI355X (gfx950) implementation of the hot
+ * path of the Intrusive Polynomial Moment (IPM) method for hyperbolic
+ * conservation laws with uncertain initial data (Kusch, Wolters, Frank,
+ * arXiv:1912.09238).
+ *
+ * One call to ipm_step advances each listed problem by up to max_steps time
+ * steps.  A time step is, for every cell j,
+ *   1. the dual solve lambda_j = argmin L(lambda; uhat_j) of eq:L by Newton
+ *      iterations lambda <- d(lambda, uhat_j) (eq:dualIterationFunction)
+ *      until eq:tauCrit holds (Alg. 1), or exactly one Newton step in the
+ *      one-shot mode (eq:oneshotIPM, Alg. 2);
+ *   2. the kinetic numerical flux of the ansatz u_s(lambda^T phi) at the
+ *      quadrature nodes and the moment update c(lambda_l, lambda_c,
+ *      lambda_r) of eq:momentIterationFunction in the quadrature form
+ *      eq:momentUpQuadrature (Sec. 3.1 and Sec. 6);
+ * with the time step dt = CFL dx / a_max taken from the largest wave speed
+ * of the current ansatz over all cells and nodes (2D: CFL / (a_x/dx +
+ * a_y/dy)), the last step clipped to t_end.  Every step runs in HIP kernels
+ * on the device; the host only enqueues.
+ *
+ * Conventions
+ *  - Every call returns an ipm_status; the message of the last failure is
+ *    ipm_last_error(ctx).
+ *  - Host input arrays are read and copied during the call; the caller keeps
+ *    ownership.  Device state is owned by the context.
+ *  - Moment and dual arrays use the layout [cell][m][N]: cell-major, then
+ *    the m conserved variables, then the N basis functions in graded order
+ *    (total degree ascending, first exponent descending; phi_0 = 1 first).
+ *    Cells are numbered c = iy * nx + ix.  Nodal arrays are [cell][Q][m]
+ *    with the tensor Gauss-Legendre nodes in the order ipm_quadrature gives.
+ *  - ipm_step is asynchronous on the context's stream unless info != NULL.
+ *  - A numerical failure of a problem (Newton not converged, ansatz outside
+ *    the entropy's domain, non-finite values) is sticky for that problem and
+ *    stops it; other problems go on.
+ *  - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef IPM_H
+#define IPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipm_ctx ipm_ctx;
+
+typedef enum {
+  IPM_OK = 0,
+  IPM_E_ARG = -1,           /* invalid argument (message names it) */
+  IPM_E_STATE = -2,         /* unknown problem id or call out of order */
+  IPM_E_NOMEM = -3,         /* device memory or admission budget exhausted */
+  IPM_E_REALIZABILITY = -4, /* ansatz outside the closure's domain */
+  IPM_E_NEWTON = -5,        /* dual not converged within max_newton */
+  IPM_E_NONFINITE = -6,     /* NaN/Inf in the state */
+  IPM_E_DEVICE = -7,        /* HIP runtime error */
+  IPM_E_BUSY = -8           /* no free problem slot */
+} ipm_status;
+
+enum { IPM_BURGERS_1D = 0, IPM_EULER_1D = 1, IPM_EULER_2D = 2 };
+/* entropies (Sec. 2 eq:primalProblem): quadratic |u|^2/2 gives stochastic
+   Galerkin; log-barrier (u-u_-)ln(u-u_-)+(u_+-u)ln(u_+-u) for scalar
+   problems; the Euler entropy -rho ln(rho^-gamma (E-|m|^2/(2 rho))) of App. B */
+enum { IPM_ENT_QUADRATIC = 0, IPM_ENT_LOG_BARRIER = 1, IPM_ENT_EULER = 2 };
+/* deterministic numerical flux g of the kinetic flux eq:numericalFluxIPM */
+enum { IPM_FLUX_LF = 0, IPM_FLUX_RUSANOV = 1 };
+enum { IPM_BC_OUTFLOW = 0, IPM_BC_PERIODIC = 1, IPM_BC_DIRICHLET = 2 };
+/* arithmetic of the Hessian assembly (Newton update, Cholesky solve, gradient
+   and the tau test are always FP64) */
+enum { IPM_PREC_FP64 = 0, IPM_PREC_FP32 = 1, IPM_PREC_BF16 = 2 };
+
+typedef struct {
+  int device;               /* HIP device ordinal */
+  void *hip_stream;         /* hipStream_t to order all work on; NULL: own stream */
+  size_t hbm_budget_bytes;  /* admission limit for all problems (0: no limit) */
+  int max_problems;         /* problem slots (0: 1024) */
+} ipm_config;
+
+typedef struct {
+  int equation;             /* IPM_BURGERS_1D | IPM_EULER_1D | IPM_EULER_2D */
+  int entropy;              /* IPM_ENT_* (Burgers: quadratic or log-barrier; Euler: quadratic or Euler) */
+  int flux;                 /* IPM_FLUX_* */
+  double gamma;             /* ratio of specific heats (Euler), > 1 */
+  double u_minus, u_plus;   /* log-barrier bounds, u_minus < u_plus */
+  int p;                    /* uncertain dimensions, 1..3; xi ~ U(-1,1)^p */
+  int degree;               /* total degree M; N = binomial(M+p, p) (eq:numberBasisFcts) */
+  const int8_t *cell_degree;/* optional [cells] per-cell total degree in 0..degree (NULL: uniform) */
+  int quad_per_dim;         /* tensor Gauss-Legendre points per dimension; Q = quad_per_dim^p */
+  double cfl;               /* dt = cfl * dx / a_max */
+  double t_end;             /* stop time (> 0), or 0 for no time limit */
+  double tau;               /* dual tolerance of eq:tauCrit (absolute) */
+  double steady_eps;        /* stop when eq:residualSteady <= steady_eps (0: never) */
+  int max_newton;           /* Newton iterations per cell and step before IPM_E_NEWTON */
+  int one_shot;             /* 1: one Newton step per time step (Alg. 2) */
+  int precision;            /* IPM_PREC_* */
+  int nx, ny;               /* cells per direction (ny = 1 in 1D) */
+  double x0, x1, y0, y1;    /* domain */
+  int bc[4];                /* x-, x+, y-, y+ (periodic must be paired) */
+  const double *ic_nodal;   /* [cells][Q][m] u_IC at cell centres and nodes, or NULL */
+  const double *ic_moments; /* [cells][m][N] initial moments (used if ic_nodal == NULL) */
+  const double *ic_dual;    /* optional [cells][m][N] warm start of the dual (resume) */
+  const double *dirichlet;  /* [4][Q][m] nodal ghost states of Dirichlet sides, or NULL */
+} ipm_problem;
+
+typedef struct {
+  int status;               /* ipm_status of the problem (sticky) */
+  int done;                 /* reached t_end or steady_eps, or failed */
+  long long steps;          /* completed time steps */
+  double t, dt;             /* time reached, last time step */
+  double residual;          /* last eq:residualSteady value */
+  double amax;              /* last largest wave speed */
+  long long newton_iters;   /* Newton updates summed over cells and steps */
+  long long cell_updates;   /* cells x completed steps */
+  int max_iters;            /* largest Newton count of one cell in one step */
+} ipm_step_info;
+
+/* Create a context on cfg->device.  *out receives the handle. */
+ipm_status ipm_create(const ipm_config *cfg, ipm_ctx **out);
+
+/* Release every problem and the context. */
+ipm_status ipm_destroy(ipm_ctx *ctx);
+
+/* Tensor Gauss-Legendre rule for xi ~ U(-1,1)^p (Sec. 3.1 quadrature
+   <h>_Q with the density folded into the weights, so sum(weights) = 1):
+   nodes [Q][p] with the first coordinate varying slowest.  cap = capacity of
+   weights in entries; returns IPM_E_ARG if Q > cap.  Host only, no device. */
+ipm_status ipm_quadrature(int p, int quad_per_dim, double *nodes, double *weights, int cap);
+
+/* Number of basis functions N = binomial(degree + p, p). */
+int ipm_basis_size(int p, int degree);
+
+/* Basis table Phi [Q][N], Phi[q][i] = phi_i(xi_q), of the orthonormal
+   total-degree Legendre basis (Sec. 2, gPC basis; App. A table A) at the
+   nodes of ipm_quadrature, as the library uploads it.  cap = capacity of Phi
+   in entries.  Host only, no device. */
+ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double *Phi, int cap);
+
+/* Copy a problem to the device: tables, IC projection (Alg. 1 first loop),
+   initial dual from the entropy variables, converged to tau.  Synchronous.
+   IPM_E_NOMEM when the problem does not fit the HBM budget (admission). */
+ipm_status ipm_set_problem(ipm_ctx *ctx, const ipm_problem *pb, int *problem_id);
+
+/* Enqueue up to max_steps time steps for each of the n_ids problems.
+   Steps after a problem is done are skipped on the device.  If info is not
+   NULL the call waits and fills info[k] for ids[k]. */
+ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
+                    ipm_step_info *info);
+
+/* Wait for the context's stream and fill *info for one problem. */
+ipm_status ipm_query(ipm_ctx *ctx, int id, ipm_step_info *info);
+
+/* Current moments [cells][m][N] of a problem (modes above a cell's degree are
+   zero).  out_is_device: out is a device pointer (copy ordered on the
+   context stream, asynchronous) or a host pointer (synchronous).
+   out_len = capacity of out in doubles. */
+ipm_status ipm_moments(ipm_ctx *ctx, int id, double *out, size_t out_len, int out_is_device);
+
+/* Current dual state [cells][m][N] (checkpoint; pass back as ic_dual). */
+ipm_status ipm_dual(ipm_ctx *ctx, int id, double *out, size_t out_len, int out_is_device);
+
+/* Sizes of a problem: conserved variables, basis functions, nodes, cells. */
+ipm_status ipm_problem_sizes(ipm_ctx *ctx, int id, int *m, int *N, int *Q, int *cells);
+
+/* Bytes of device memory a problem would take (admission estimate). */
+size_t ipm_problem_footprint(const ipm_problem *pb);
+
+/* Free a problem's slot and device memory. */
+ipm_status ipm_release(ipm_ctx *ctx, int id);
+
+/* Kernel timing with HIP events on the context's stream.  enable = 1 clears
+   the record and brackets every following dual-solve and update launch with
+   its own event pair; enable = 0 waits for the stream, returns the summed
+   device time of the dual-solve and of the update kernels in milliseconds
+   and the number of steps recorded, and stops recording. */
+ipm_status ipm_kernel_timing(ipm_ctx *ctx, int enable, double *dual_ms, double *update_ms,
+                             long long *launches);
+
+/* Message of the last failing call on ctx (owned by ctx, valid until the
+   next call).  ctx may be NULL for errors of ipm_create. */
+const char *ipm_last_error(const ipm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,789 @@
+// libipm: C ABI, problem state on the device, kernel dispatch.
+//
+// The host validates problems, builds the quadrature and basis tables once
+// per problem, and enqueues kernels; every step of the method (IC
+// projection, dual solves, flux quadrature, moment update, time step,
+// residual) runs on the GPU.  See include/ipm.h for the ABI contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ipm.h"
+#include "dual_small.hpp"
+#include "setup.hpp"
+#include "tables.hpp"
+#include "update.hpp"
+
+using namespace ipm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Problem {
+  int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, NP = 8, UG = 16;
+  int nx = 1, ny = 1, cells = 1;
+  int flux = 0, max_newton = 100, one_shot = 0, precision = 0;
+  int bc[4] = {0, 0, 0, 0};
+  double cfl = 0.5, t_end = 0.0, tau = 1e-10, steady_eps = 0.0;
+  double dx = 1.0, dy = 1.0, vol = 1.0;
+  ClosureParams cp{};
+  bool uneven = false;
+  double* d_phi = nullptr;
+  double* d_wphi = nullptr;
+  double* d_u[2] = {nullptr, nullptr};
+  double* d_lam = nullptr;
+  double* d_nodal = nullptr;
+  double* d_ghost = nullptr;
+  double* d_res = nullptr;
+  int8_t* d_cellN = nullptr;
+  StepCtrl* d_ctrl = nullptr;
+  long long step_index = 0;
+  size_t bytes = 0;
+  int dual_waves = 4, upd_blocks = 1, dual_blocks = 1;
+  size_t dual_lds = 0, upd_lds = 0;
+};
+
+}  // namespace
+
+struct ipm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  int max_problems = 1024;
+  std::vector<std::unique_ptr<Problem>> problems;
+  std::string err;
+  size_t max_lds = 64 * 1024;  // dynamic LDS bytes one block may use
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs: dual start/stop, update start/stop
+  size_t ev_used = 0;
+};
+
+namespace {
+
+ipm_status fail(ipm_ctx* ctx, ipm_status st, const std::string& msg) {
+  if (ctx)
+    ctx->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                            \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(ctx, IPM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int components(int eq) { return eq == IPM_BURGERS_1D ? 1 : (eq == IPM_EULER_1D ? 3 : 4); }
+
+int pow2_at_least(int n, int lo) {
+  int v = lo;
+  while (v < n) v <<= 1;
+  return v;
+}
+
+using DualFn = void (*)(DualParams);
+using UpdFn = void (*)(UpdateParams);
+using SetupFn = void (*)(SetupParams);
+
+template <int M>
+DualFn dual_fn(int NP) {
+  switch (NP) {
+    case 8: return dual_small_kernel<M, 8>;
+    case 16: return dual_small_kernel<M, 16>;
+    case 32: return dual_small_kernel<M, 32>;
+    case 64: return dual_small_kernel<M, 64>;
+  }
+  return nullptr;
+}
+
+DualFn pick_dual(int M, int NP) {
+  if (M == 1) return dual_fn<1>(NP);
+  if (M == 3) return dual_fn<3>(NP);
+  if (M == 4) return dual_fn<4>(NP);
+  return nullptr;
+}
+
+template <int M>
+UpdFn upd_fn(int G) {
+  switch (G) {
+    case 16: return update_kernel<M, 16>;
+    case 32: return update_kernel<M, 32>;
+    case 64: return update_kernel<M, 64>;
+  }
+  return nullptr;
+}
+
+UpdFn pick_update(int M, int G) {
+  if (M == 1) return upd_fn<1>(G);
+  if (M == 3) return upd_fn<3>(G);
+  if (M == 4) return upd_fn<4>(G);
+  return nullptr;
+}
+
+SetupFn pick_setup(int M) {
+  if (M == 1) return setup_kernel<1>;
+  if (M == 3) return setup_kernel<3>;
+  return setup_kernel<4>;
+}
+
+size_t dual_lds_bytes(int M, int NP, int Q, int kp, int waves) {
+  auto f = [&](auto tag) -> size_t {
+    constexpr int MM = decltype(tag)::value;
+    switch (NP) {
+      case 8: return SmallDual<MM, 8>::lds_bytes(Q, kp, waves);
+      case 16: return SmallDual<MM, 16>::lds_bytes(Q, kp, waves);
+      case 32: return SmallDual<MM, 32>::lds_bytes(Q, kp, waves);
+      default: return SmallDual<MM, 64>::lds_bytes(Q, kp, waves);
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  if (M == 3) return f(std::integral_constant<int, 3>{});
+  return f(std::integral_constant<int, 4>{});
+}
+
+Problem* get(ipm_ctx* ctx, int id) {
+  if (!ctx || id < 0 || id >= static_cast<int>(ctx->problems.size())) return nullptr;
+  return ctx->problems[id].get();
+}
+
+void free_problem(Problem* P) {
+  if (!P) return;
+  void* ptrs[] = {P->d_phi, P->d_wphi, P->d_u[0], P->d_u[1], P->d_lam, P->d_nodal,
+                  P->d_ghost, P->d_res, P->d_cellN, P->d_ctrl};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+// Launch geometry of a problem's kernels.
+ipm_status plan(ipm_ctx* ctx, Problem& P) {
+  const int n = P.M * P.N;
+  if (n > 64)
+    return fail(ctx, IPM_E_ARG,
+                "m*N = " + std::to_string(n) + " unknowns per cell exceeds 64 (supported range of the "
+                "fused dual kernel)");
+  P.NP = pow2_at_least(n, 8);
+  P.kp = std::max(P.N, (P.NP + P.M - 1) / P.M);
+  int waves = 4;
+  while (waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, waves) > 64 * 1024) waves >>= 1;
+  P.dual_waves = waves;
+  P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, waves);
+  if (P.dual_lds > ctx->max_lds)
+    return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
+                                    std::to_string(P.Q) + ")");
+  const int cpb = waves * (64 / P.NP);
+  P.dual_blocks = (P.cells + cpb - 1) / cpb;
+  P.UG = pow2_at_least(std::min(64, std::max(P.Q, n)), 16);
+  const int ucpb = 4 * (64 / P.UG);
+  P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
+  P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
+                                static_cast<size_t>(ucpb) * P.Q * P.M + 256);
+  if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
+  return IPM_OK;
+}
+
+DualParams dual_params(const Problem& P, int mode, int parity, const double* uhat, double* lam,
+                       double* nodal, int cells, const int8_t* cellN, StepCtrl* ctrl) {
+  DualParams d{};
+  d.phi = P.d_phi;
+  d.wphi = P.d_wphi;
+  d.N = P.N;
+  d.Q = P.Q;
+  d.kp = P.kp;
+  d.cells = cells;
+  d.cellN = cellN;
+  d.uhat = uhat;
+  d.lam = lam;
+  d.nodal = nodal;
+  d.cp = P.cp;
+  d.tau = P.tau;
+  d.max_newton = P.max_newton;
+  d.one_shot = mode == 0 ? P.one_shot : 0;
+  d.mode = mode;
+  d.dim = P.dim;
+  d.ctrl = ctrl;
+  d.parity = parity;
+  return d;
+}
+
+ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int cells) {
+  DualFn fn = pick_dual(P.M, P.NP);
+  if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
+  const int cpb = P.dual_waves * (64 / P.NP);
+  const int blocks = (cells + cpb - 1) / cpb;
+  if (blocks == 0) return IPM_OK;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * P.dual_waves), P.dual_lds, ctx->stream, d);
+  HIPCHK(ctx, hipGetLastError());
+  return IPM_OK;
+}
+
+ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
+  const int parity = static_cast<int>(P.step_index & 1);
+  DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
+                             P.d_cellN, P.d_ctrl);
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+  if (ctx->timing) {
+    while (ctx->ev.size() < ctx->ev_used + 4) {
+      hipEvent_t e;
+      HIPCHK(ctx, hipEventCreate(&e));
+      ctx->ev.push_back(e);
+    }
+    e0 = ctx->ev[ctx->ev_used];
+    e1 = ctx->ev[ctx->ev_used + 1];
+    e2 = ctx->ev[ctx->ev_used + 2];
+    e3 = ctx->ev[ctx->ev_used + 3];
+    ctx->ev_used += 4;
+    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+  }
+  ipm_status st = launch_dual(ctx, P, d, P.cells);
+  if (st != IPM_OK) return st;
+  if (ctx->timing) {
+    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(e2, ctx->stream));
+  }
+  UpdateParams u{};
+  u.wphi = P.d_wphi;
+  u.N = P.N;
+  u.Q = P.Q;
+  u.kp = P.kp;
+  u.cells = P.cells;
+  u.nx = P.nx;
+  u.ny = P.ny;
+  u.dim = P.dim;
+  u.cellN = P.d_cellN;
+  u.nodal = P.d_nodal;
+  u.ghost = P.d_ghost;
+  u.uold = P.d_u[parity];
+  u.unew = P.d_u[parity ^ 1];
+  u.res_part = P.d_res;
+  for (int k = 0; k < 4; ++k) u.bc[k] = P.bc[k];
+  u.flux = P.flux;
+  u.gamma = P.cp.gamma;
+  u.cfl = P.cfl;
+  u.dx = P.dx;
+  u.dy = P.dy;
+  u.vol = P.vol;
+  u.t_end = P.t_end;
+  u.steady_eps = P.steady_eps;
+  u.ctrl = P.d_ctrl;
+  u.parity = parity;
+  UpdFn fn = pick_update(P.M, P.UG);
+  hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(256), P.upd_lds, ctx->stream, u);
+  HIPCHK(ctx, hipGetLastError());
+  if (ctx->timing) HIPCHK(ctx, hipEventRecord(e3, ctx->stream));
+  ++P.step_index;
+  return IPM_OK;
+}
+
+ipm_status set_kernel_attributes(ipm_ctx* ctx) {
+  static bool done = false;
+  if (done) return IPM_OK;
+  const int big = static_cast<int>(ctx->max_lds);
+  // raise the dynamic LDS limit above the 64 KiB default (best effort)
+  for (int M : {1, 3, 4})
+    for (int NP : {8, 16, 32, 64})
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_dual(M, NP)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  for (int M : {1, 3, 4})
+    for (int G : {16, 32, 64})
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipGetLastError();  // the request is best effort; do not leave a sticky error
+  done = true;
+  return IPM_OK;
+}
+
+ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
+  if (!pb) return fail(ctx, IPM_E_ARG, "problem is NULL");
+  if (pb->equation < 0 || pb->equation > 2) return fail(ctx, IPM_E_ARG, "equation out of range");
+  const int M = components(pb->equation);
+  if (M == 1 && pb->entropy != IPM_ENT_QUADRATIC && pb->entropy != IPM_ENT_LOG_BARRIER)
+    return fail(ctx, IPM_E_ARG, "Burgers needs the quadratic or the log-barrier entropy");
+  if (M > 1 && pb->entropy != IPM_ENT_QUADRATIC && pb->entropy != IPM_ENT_EULER)
+    return fail(ctx, IPM_E_ARG, "Euler needs the quadratic or the Euler entropy");
+  if (pb->flux != IPM_FLUX_LF && pb->flux != IPM_FLUX_RUSANOV)
+    return fail(ctx, IPM_E_ARG, "flux out of range");
+  if (pb->p < 1 || pb->p > 3) return fail(ctx, IPM_E_ARG, "p must be 1..3");
+  if (pb->degree < 0 || pb->degree > 40) return fail(ctx, IPM_E_ARG, "degree must be 0..40");
+  if (pb->quad_per_dim < 1 || pb->quad_per_dim > 64)
+    return fail(ctx, IPM_E_ARG, "quad_per_dim must be 1..64");
+  if (pb->precision < 0 || pb->precision > 2) return fail(ctx, IPM_E_ARG, "precision out of range");
+  if (pb->precision != IPM_PREC_FP64)
+    return fail(ctx, IPM_E_ARG, "reduced-precision Hessian assembly needs the MFMA path (m*N > 64)");
+  if (!(pb->cfl > 0.0)) return fail(ctx, IPM_E_ARG, "cfl must be > 0");
+  if (!(pb->tau > 0.0)) return fail(ctx, IPM_E_ARG, "tau must be > 0");
+  if (pb->t_end < 0.0 || pb->steady_eps < 0.0)
+    return fail(ctx, IPM_E_ARG, "t_end and steady_eps must be >= 0");
+  if (pb->max_newton < 1) return fail(ctx, IPM_E_ARG, "max_newton must be >= 1");
+  if (pb->nx < 1) return fail(ctx, IPM_E_ARG, "nx must be >= 1");
+  if (pb->equation == IPM_EULER_2D && pb->ny < 1) return fail(ctx, IPM_E_ARG, "ny must be >= 1");
+  if (!(pb->x1 > pb->x0)) return fail(ctx, IPM_E_ARG, "x1 must exceed x0");
+  if (pb->equation == IPM_EULER_2D && !(pb->y1 > pb->y0))
+    return fail(ctx, IPM_E_ARG, "y1 must exceed y0");
+  if (M > 1 && !(pb->gamma > 1.0)) return fail(ctx, IPM_E_ARG, "gamma must be > 1");
+  if (pb->entropy == IPM_ENT_LOG_BARRIER && !(pb->u_plus > pb->u_minus))
+    return fail(ctx, IPM_E_ARG, "log-barrier needs u_minus < u_plus");
+  const int sides = pb->equation == IPM_EULER_2D ? 4 : 2;
+  for (int s = 0; s < sides; ++s)
+    if (pb->bc[s] < 0 || pb->bc[s] > 2) return fail(ctx, IPM_E_ARG, "bc out of range");
+  for (int s = 0; s < sides; s += 2)
+    if ((pb->bc[s] == IPM_BC_PERIODIC) != (pb->bc[s + 1] == IPM_BC_PERIODIC))
+      return fail(ctx, IPM_E_ARG, "periodic boundaries must be paired");
+  bool any_dir = false;
+  for (int s = 0; s < sides; ++s) any_dir |= pb->bc[s] == IPM_BC_DIRICHLET;
+  if (any_dir && !pb->dirichlet) return fail(ctx, IPM_E_ARG, "Dirichlet sides need dirichlet states");
+  if (!pb->ic_nodal && !pb->ic_moments) return fail(ctx, IPM_E_ARG, "need ic_nodal or ic_moments");
+  return IPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ipm_last_error(const ipm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int ipm_basis_size(int p, int degree) {
+  if (p < 1 || degree < 0) return 0;
+  return binom_basis(p, degree);
+}
+
+ipm_status ipm_quadrature(int p, int quad_per_dim, double* nodes, double* weights, int cap) {
+  if (p < 1 || p > 3 || quad_per_dim < 1 || quad_per_dim > 64 || !nodes || !weights)
+    return fail(nullptr, IPM_E_ARG, "ipm_quadrature: bad arguments");
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= quad_per_dim;
+  if (Q > cap) return fail(nullptr, IPM_E_ARG, "ipm_quadrature: capacity too small");
+  std::vector<double> x, w;
+  tensor_rule(p, quad_per_dim, x, w);
+  std::memcpy(nodes, x.data(), sizeof(double) * Q * p);
+  std::memcpy(weights, w.data(), sizeof(double) * Q);
+  return IPM_OK;
+}
+
+// Host copy of the basis table Phi [Q][N] the library uploads (inspection).
+ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double* Phi, int cap) {
+  if (p < 1 || p > 3 || degree < 0 || quad_per_dim < 1 || quad_per_dim > 64 || !Phi)
+    return fail(nullptr, IPM_E_ARG, "ipm_basis_table: bad arguments");
+  std::vector<double> x, w;
+  const int Q = tensor_rule(p, quad_per_dim, x, w);
+  const int N = binom_basis(p, degree);
+  if (static_cast<long long>(Q) * N > cap)
+    return fail(nullptr, IPM_E_ARG, "ipm_basis_table: capacity too small");
+  std::vector<double> t = basis_table(p, degree, Q, x);
+  std::memcpy(Phi, t.data(), sizeof(double) * Q * N);
+  return IPM_OK;
+}
+
+size_t ipm_problem_footprint(const ipm_problem* pb) {
+  if (!pb) return 0;
+  const int M = components(pb->equation);
+  const int N = binom_basis(pb->p, pb->degree);
+  int Q = 1;
+  for (int k = 0; k < pb->p; ++k) Q *= pb->quad_per_dim;
+  const size_t cells = static_cast<size_t>(pb->nx) * (pb->equation == IPM_EULER_2D ? pb->ny : 1);
+  const size_t n = static_cast<size_t>(M) * N;
+  return sizeof(double) * (3 * cells * n + cells * Q * M + 2 * static_cast<size_t>(Q) * (N + 64) +
+                           4 * static_cast<size_t>(Q) * M + cells / 8 + 64) +
+         cells + sizeof(StepCtrl);
+}
+
+ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, IPM_E_ARG, "ipm_create: NULL argument");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return fail(nullptr, IPM_E_DEVICE, "ipm_create: no HIP device available");
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, IPM_E_ARG, "ipm_create: bad device");
+  auto ctx = std::make_unique<ipm_ctx>();
+  ctx->device = cfg->device;
+  ctx->budget = cfg->hbm_budget_bytes;
+  ctx->max_problems = cfg->max_problems > 0 ? cfg->max_problems : 1024;
+  e = hipSetDevice(cfg->device);
+  if (e != hipSuccess) return fail(nullptr, IPM_E_DEVICE, hipGetErrorString(e));
+  if (cfg->hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(cfg->hip_stream);
+  } else {
+    e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(nullptr, IPM_E_DEVICE, hipGetErrorString(e));
+    ctx->own_stream = true;
+  }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, cfg->device) ==
+          hipSuccess &&
+      lds > 0)
+    ctx->max_lds = static_cast<size_t>(lds);
+  (void)hipGetLastError();
+  if (set_kernel_attributes(ctx.get()) != IPM_OK) return fail(nullptr, IPM_E_DEVICE, ctx->err);
+  *out = ctx.release();
+  return IPM_OK;
+}
+
+ipm_status ipm_destroy(ipm_ctx* ctx) {
+  if (!ctx) return IPM_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->problems) free_problem(p.get());
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return IPM_OK;
+}
+
+ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id) {
+  if (!ctx || !problem_id) return fail(ctx, IPM_E_ARG, "NULL argument");
+  ipm_status st = validate(ctx, pb);
+  if (st != IPM_OK) return st;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  auto up = std::make_unique<Problem>();
+  Problem& P = *up;
+  P.eq = pb->equation;
+  P.M = components(pb->equation);
+  P.dim = pb->equation == IPM_EULER_2D ? 2 : 1;
+  P.p = pb->p;
+  P.degree = pb->degree;
+  P.N = binom_basis(pb->p, pb->degree);
+  std::vector<double> nodes, w;
+  P.Q = tensor_rule(pb->p, pb->quad_per_dim, nodes, w);
+  P.nx = pb->nx;
+  P.ny = P.dim == 2 ? pb->ny : 1;
+  P.cells = P.nx * P.ny;
+  P.flux = pb->flux;
+  P.max_newton = pb->max_newton;
+  P.one_shot = pb->one_shot ? 1 : 0;
+  P.precision = pb->precision;
+  for (int k = 0; k < 4; ++k) P.bc[k] = (P.dim == 1 && k >= 2) ? IPM_BC_OUTFLOW : pb->bc[k];
+  P.cfl = pb->cfl;
+  P.t_end = pb->t_end;
+  P.tau = pb->tau;
+  P.steady_eps = pb->steady_eps;
+  P.dx = (pb->x1 - pb->x0) / pb->nx;
+  P.dy = P.dim == 2 ? (pb->y1 - pb->y0) / pb->ny : 1.0;
+  P.vol = P.dim == 2 ? P.dx * P.dy : P.dx;
+  P.cp.entropy = pb->entropy;
+  P.cp.gamma = pb->gamma;
+  P.cp.um = pb->u_minus;
+  P.cp.up = pb->u_plus;
+  P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
+  std::vector<int8_t> cellN;
+  if (pb->cell_degree) {
+    cellN.resize(P.cells);
+    for (int c = 0; c < P.cells; ++c) {
+      const int dg = pb->cell_degree[c];
+      if (dg < 0 || dg > pb->degree) return fail(ctx, IPM_E_ARG, "cell_degree out of range");
+      cellN[c] = static_cast<int8_t>(binom_basis(pb->p, dg));
+    }
+    P.uneven = true;
+  }
+  st = plan(ctx, P);
+  if (st != IPM_OK) return st;
+
+  const size_t fp = ipm_problem_footprint(pb);
+  if (ctx->budget && ctx->used + fp > ctx->budget)
+    return fail(ctx, IPM_E_NOMEM, "problem does not fit the HBM budget");
+  int slot = -1;
+  for (size_t k = 0; k < ctx->problems.size(); ++k)
+    if (!ctx->problems[k]) {
+      slot = static_cast<int>(k);
+      break;
+    }
+  if (slot < 0) {
+    if (static_cast<int>(ctx->problems.size()) >= ctx->max_problems)
+      return fail(ctx, IPM_E_BUSY, "no free problem slot");
+    ctx->problems.emplace_back();
+    slot = static_cast<int>(ctx->problems.size()) - 1;
+  }
+
+  // tables: Phi and w*Phi, zero padded to kp columns
+  const std::vector<double> phi = basis_table(pb->p, pb->degree, P.Q, nodes);
+  std::vector<double> phip(static_cast<size_t>(P.Q) * P.kp, 0.0), wphip(phip.size(), 0.0);
+  for (int q = 0; q < P.Q; ++q)
+    for (int i = 0; i < P.N; ++i) {
+      phip[static_cast<size_t>(q) * P.kp + i] = phi[static_cast<size_t>(q) * P.N + i];
+      wphip[static_cast<size_t>(q) * P.kp + i] = w[q] * phi[static_cast<size_t>(q) * P.N + i];
+    }
+  const size_t cn = static_cast<size_t>(P.cells) * P.M * P.N;
+  const size_t nod = static_cast<size_t>(P.cells) * P.Q * P.M;
+  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    P.bytes += bytes;
+    return hipMalloc(ptr, std::max<size_t>(bytes, 8));
+  };
+  auto cleanup = [&](ipm_status s) {
+    free_problem(&P);
+    return s;
+  };
+#define ALLOC(ptr, bytes)                                                        \
+  do {                                                                           \
+    if (alloc(reinterpret_cast<void**>(&(ptr)), (bytes)) != hipSuccess)          \
+      return cleanup(fail(ctx, IPM_E_NOMEM, "device allocation failed"));        \
+  } while (0)
+  ALLOC(P.d_phi, phip.size() * sizeof(double));
+  ALLOC(P.d_wphi, wphip.size() * sizeof(double));
+  ALLOC(P.d_u[0], cn * sizeof(double));
+  ALLOC(P.d_u[1], cn * sizeof(double));
+  ALLOC(P.d_lam, cn * sizeof(double));
+  ALLOC(P.d_nodal, nod * sizeof(double));
+  ALLOC(P.d_ghost, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double));
+  ALLOC(P.d_res, static_cast<size_t>(P.upd_blocks) * sizeof(double));
+  ALLOC(P.d_ctrl, sizeof(StepCtrl));
+  if (P.uneven) ALLOC(P.d_cellN, static_cast<size_t>(P.cells));
+#undef ALLOC
+  hipStream_t s = ctx->stream;
+#define CHK(expr)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return cleanup(fail(ctx, IPM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  CHK(hipMemcpyAsync(P.d_phi, phip.data(), phip.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  CHK(hipMemcpyAsync(P.d_wphi, wphip.data(), wphip.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (P.uneven)
+    CHK(hipMemcpyAsync(P.d_cellN, cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
+  CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  CHK(hipMemsetAsync(P.d_ghost, 0, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double), s));
+  CHK(hipMemsetAsync(P.d_nodal, 0, nod * sizeof(double), s));
+
+  // staging of the host inputs
+  double* d_in = nullptr;
+  double* d_dual = nullptr;
+  const size_t in_len = pb->ic_nodal ? nod : cn;
+  CHK(hipMalloc(&d_in, in_len * sizeof(double)));
+  CHK(hipMemcpyAsync(d_in, pb->ic_nodal ? pb->ic_nodal : pb->ic_moments, in_len * sizeof(double),
+                     hipMemcpyHostToDevice, s));
+  if (pb->ic_dual) {
+    CHK(hipMalloc(&d_dual, cn * sizeof(double)));
+    CHK(hipMemcpyAsync(d_dual, pb->ic_dual, cn * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  SetupParams sp{};
+  sp.wphi = P.d_wphi;
+  sp.N = P.N;
+  sp.Q = P.Q;
+  sp.kp = P.kp;
+  sp.cells = P.cells;
+  sp.cellN = P.d_cellN;
+  sp.ic_nodal = pb->ic_nodal ? d_in : nullptr;
+  sp.ic_moments = pb->ic_nodal ? nullptr : d_in;
+  sp.ic_dual = d_dual;
+  sp.uhat = P.d_u[0];
+  sp.lam = P.d_lam;
+  sp.cp = P.cp;
+  sp.status = &P.d_ctrl->setup_status;
+  {
+    const size_t total = cn;
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    if (blocks) hipLaunchKernelGGL(pick_setup(P.M), dim3(blocks), dim3(256), 0, s, sp);
+    CHK(hipGetLastError());
+  }
+  // converge the initial dual (setup mode of the dual kernel)
+  {
+    DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN, P.d_ctrl);
+    st = launch_dual(ctx, P, d, P.cells);
+    if (st != IPM_OK) return cleanup(st);
+  }
+  // Dirichlet ghosts: fixed moments, converged dual, their nodal ansatz and speeds
+  int dsides[4], nd = 0;
+  for (int k = 0; k < 4; ++k)
+    if (P.bc[k] == IPM_BC_DIRICHLET) dsides[nd++] = k;
+  double gax = 0.0, gay = 0.0;
+  if (nd > 0) {
+    const size_t gq = static_cast<size_t>(P.Q) * P.M;
+    std::vector<double> gin(nd * gq);
+    for (int k = 0; k < nd; ++k)
+      std::memcpy(&gin[k * gq], pb->dirichlet + dsides[k] * gq, gq * sizeof(double));
+    double *d_gin = nullptr, *d_gu = nullptr, *d_gl = nullptr, *d_gn = nullptr;
+    StepCtrl* d_gc = nullptr;
+    CHK(hipMalloc(&d_gin, gin.size() * sizeof(double)));
+    CHK(hipMalloc(&d_gu, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
+    CHK(hipMalloc(&d_gl, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
+    CHK(hipMalloc(&d_gn, gin.size() * sizeof(double)));
+    CHK(hipMalloc(&d_gc, sizeof(StepCtrl)));
+    CHK(hipMemsetAsync(d_gc, 0, sizeof(StepCtrl), s));
+    CHK(hipMemcpyAsync(d_gin, gin.data(), gin.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    SetupParams gp = sp;
+    gp.cells = nd;
+    gp.cellN = nullptr;
+    gp.ic_nodal = d_gin;
+    gp.ic_moments = nullptr;
+    gp.ic_dual = nullptr;
+    gp.uhat = d_gu;
+    gp.lam = d_gl;
+    gp.status = &d_gc->setup_status;
+    hipLaunchKernelGGL(pick_setup(P.M), dim3(1), dim3(256), 0, s, gp);
+    CHK(hipGetLastError());
+    DualParams d1 = dual_params(P, 1, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc);
+    st = launch_dual(ctx, P, d1, nd);
+    if (st != IPM_OK) return cleanup(st);
+    DualParams d0 = dual_params(P, 0, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc);
+    d0.one_shot = 0;
+    st = launch_dual(ctx, P, d0, nd);
+    if (st != IPM_OK) return cleanup(st);
+    for (int k = 0; k < nd; ++k)
+      CHK(hipMemcpyAsync(P.d_ghost + dsides[k] * gq, d_gn + k * gq, gq * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+    StepCtrl gc;
+    CHK(hipMemcpyAsync(&gc, d_gc, sizeof(StepCtrl), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    (void)hipFree(d_gin);
+    (void)hipFree(d_gu);
+    (void)hipFree(d_gl);
+    (void)hipFree(d_gn);
+    (void)hipFree(d_gc);
+    if (gc.setup_status || gc.status)
+      return cleanup(fail(ctx, IPM_E_REALIZABILITY, "Dirichlet ghost state has no admissible dual"));
+    for (int k = 0; k < 64; ++k) {
+      gax = std::max(gax, __builtin_bit_cast(double, gc.amax[0][0][k]));
+      gay = std::max(gay, __builtin_bit_cast(double, gc.amax[0][1][k]));
+    }
+  }
+  StepCtrl hc;
+  CHK(hipMemcpyAsync(&hc, P.d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, s));
+  CHK(hipStreamSynchronize(s));
+  if (d_in) (void)hipFree(d_in);
+  if (d_dual) (void)hipFree(d_dual);
+  if (hc.setup_status) {
+    std::string why = (hc.setup_status & kStRealizability) ? "initial state outside the entropy's domain"
+                      : (hc.setup_status & kStNewton)      ? "initial dual did not converge"
+                                                           : "initial dual solve failed";
+    return cleanup(fail(ctx, hc.setup_status & kStRealizability ? IPM_E_REALIZABILITY : IPM_E_NEWTON,
+                        why + " (status " + std::to_string(hc.setup_status) + ")"));
+  }
+  std::memset(&hc, 0, sizeof(hc));
+  hc.ghost_amax[0] = gax;
+  hc.ghost_amax[1] = gay;
+  CHK(hipMemcpyAsync(P.d_ctrl, &hc, sizeof(StepCtrl), hipMemcpyHostToDevice, s));
+  CHK(hipStreamSynchronize(s));
+#undef CHK
+  ctx->used += P.bytes;
+  ctx->problems[slot] = std::move(up);
+  *problem_id = slot;
+  return IPM_OK;
+}
+
+ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_step_info* info) {
+  if (!ctx) return IPM_E_ARG;
+  if (n_ids < 0 || (n_ids > 0 && !ids) || max_steps < 0)
+    return fail(ctx, IPM_E_ARG, "ipm_step: bad arguments");
+  for (int k = 0; k < n_ids; ++k)
+    if (!get(ctx, ids[k])) return fail(ctx, IPM_E_STATE, "ipm_step: unknown problem id");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  for (int s = 0; s < max_steps; ++s)
+    for (int k = 0; k < n_ids; ++k) {
+      ipm_status st = enqueue_step(ctx, *get(ctx, ids[k]));
+      if (st != IPM_OK) return st;
+    }
+  if (info)
+    for (int k = 0; k < n_ids; ++k) {
+      ipm_status st = ipm_query(ctx, ids[k], &info[k]);
+      if (st != IPM_OK) return st;
+    }
+  return IPM_OK;
+}
+
+ipm_status ipm_query(ipm_ctx* ctx, int id, ipm_step_info* info) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_query: unknown problem id");
+  if (!info) return fail(ctx, IPM_E_ARG, "ipm_query: info is NULL");
+  StepCtrl hc;
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  info->done = hc.done;
+  info->steps = static_cast<long long>(hc.steps);
+  info->t = hc.t[hc.steps & 1];
+  info->dt = hc.dt_last;
+  info->residual = hc.residual;
+  info->amax = hc.amax_last;
+  info->newton_iters = static_cast<long long>(hc.newton_iters);
+  info->cell_updates = static_cast<long long>(hc.steps) * P->cells;
+  info->max_iters = static_cast<int>(hc.max_iters);
+  const unsigned st = hc.status;
+  info->status = st == 0u                  ? IPM_OK
+                 : (st & kStNonfinite)     ? IPM_E_NONFINITE
+                 : (st & kStRealizability) ? IPM_E_REALIZABILITY
+                                           : IPM_E_NEWTON;
+  return IPM_OK;
+}
+
+ipm_status ipm_moments(ipm_ctx* ctx, int id, double* out, size_t out_len, int out_is_device) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_moments: unknown problem id");
+  const size_t cn = static_cast<size_t>(P->cells) * P->M * P->N;
+  if (!out || out_len < cn) return fail(ctx, IPM_E_ARG, "ipm_moments: output too small");
+  StepCtrl hc;
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const double* src = P->d_u[hc.steps & 1];
+  HIPCHK(ctx, hipMemcpyAsync(out, src, cn * sizeof(double),
+                             out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (!out_is_device) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return IPM_OK;
+}
+
+ipm_status ipm_dual(ipm_ctx* ctx, int id, double* out, size_t out_len, int out_is_device) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_dual: unknown problem id");
+  const size_t cn = static_cast<size_t>(P->cells) * P->M * P->N;
+  if (!out || out_len < cn) return fail(ctx, IPM_E_ARG, "ipm_dual: output too small");
+  HIPCHK(ctx, hipMemcpyAsync(out, P->d_lam, cn * sizeof(double),
+                             out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (!out_is_device) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return IPM_OK;
+}
+
+ipm_status ipm_problem_sizes(ipm_ctx* ctx, int id, int* m, int* N, int* Q, int* cells) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_problem_sizes: unknown problem id");
+  if (m) *m = P->M;
+  if (N) *N = P->N;
+  if (Q) *Q = P->Q;
+  if (cells) *cells = P->cells;
+  return IPM_OK;
+}
+
+ipm_status ipm_release(ipm_ctx* ctx, int id) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_release: unknown problem id");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->used -= std::min(ctx->used, P->bytes);
+  free_problem(P);
+  ctx->problems[id].reset();
+  return IPM_OK;
+}
+
+ipm_status ipm_kernel_timing(ipm_ctx* ctx, int enable, double* dual_ms, double* update_ms,
+                             long long* launches) {
+  if (!ctx) return IPM_E_ARG;
+  if (enable) {
+    ctx->timing = true;
+    ctx->ev_used = 0;
+    return IPM_OK;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  double td = 0.0, tu = 0.0;
+  for (size_t k = 0; k + 3 < ctx->ev_used; k += 4) {
+    float a = 0.f, b = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&a, ctx->ev[k], ctx->ev[k + 1]));
+    HIPCHK(ctx, hipEventElapsedTime(&b, ctx->ev[k + 2], ctx->ev[k + 3]));
+    td += a;
+    tu += b;
+  }
+  if (dual_ms) *dual_ms = td;
+  if (update_ms) *update_ms = tu;
+  if (launches) *launches = static_cast<long long>(ctx->ev_used / 4);
+  ctx->timing = false;
+  ctx->ev_used = 0;
+  return IPM_OK;
+}
+
+}  // extern "C"

@@ -19,3 +19,27 @@ def orc():
     oracle.build()
     oracle.load()
     return oracle
+
+
+def parity(got, ref):
+    """Normwise relative L1 error per conserved variable, over cells and modes
+    (arrays [cells][m][N])."""
+    import numpy as np
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    num = np.abs(got - ref).sum(axis=(0, 2))
+    den = np.abs(ref).sum(axis=(0, 2))
+    return num / np.maximum(den, 1e-300)
+
+
+@pytest.fixture(scope="session")
+def gpu_ctx():
+    """A libipm context on cuda:0 ordered on torch's current stream."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_09238_amd import binding
+    torch.cuda.init()
+    ctx = binding.Context(device=0, stream=torch.cuda.current_stream().cuda_stream)
+    yield ctx
+    ctx.close()
