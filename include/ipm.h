@@ -73,7 +73,7 @@ enum { IPM_PREC_FP64 = 0, IPM_PREC_FP32 = 1, IPM_PREC_BF16 = 2 };
 
 typedef struct {
   int device;               /* HIP device ordinal */
-  void *hip_stream;         /* hipStream_t to order all work on; NULL: own stream */
+  void *hip_stream;         /* hipStream_t to order all work on; NULL: the null stream */
   size_t hbm_budget_bytes;  /* admission limit for all problems (0: no limit) */
   int max_problems;         /* problem slots (0: 1024) */
 } ipm_config;

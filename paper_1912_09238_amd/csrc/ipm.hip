@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "ipm.h"
-#include "dual_small.hpp"
+#include "dual.hpp"
 #include "setup.hpp"
 #include "tables.hpp"
 #include "update.hpp"
@@ -42,11 +42,14 @@ struct Problem {
   double* d_nodal = nullptr;
   double* d_ghost = nullptr;
   double* d_res = nullptr;
+  unsigned long long* d_blk = nullptr;
+  int* d_lists = nullptr;       // [2][64][list_cap] Newton lists by step parity
+  int list_cap = 0;
   int8_t* d_cellN = nullptr;
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;
-  int dual_waves = 4, upd_blocks = 1, dual_blocks = 1;
+  int upd_blocks = 1, dual_blocks = 1, dual_waves = 4;
   size_t dual_lds = 0, upd_lds = 0;
 };
 
@@ -98,13 +101,14 @@ using SetupFn = void (*)(SetupParams);
 template <int M>
 DualFn dual_fn(int NP) {
   switch (NP) {
-    case 8: return dual_small_kernel<M, 8>;
-    case 16: return dual_small_kernel<M, 16>;
-    case 32: return dual_small_kernel<M, 32>;
-    case 64: return dual_small_kernel<M, 64>;
+    case 8: return newton_kernel<M, 8>;
+    case 16: return newton_kernel<M, 16>;
+    case 32: return newton_kernel<M, 32>;
+    case 64: return newton_kernel<M, 64>;
   }
   return nullptr;
 }
+
 
 DualFn pick_dual(int M, int NP) {
   if (M == 1) return dual_fn<1>(NP);
@@ -136,14 +140,34 @@ SetupFn pick_setup(int M) {
   return setup_kernel<4>;
 }
 
+template <int M, int NP>
+using NC = NewtonCfg<M, NP>;
+
+// dynamic LDS bytes of the Newton kernel
 size_t dual_lds_bytes(int M, int NP, int Q, int kp, int waves) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
     switch (NP) {
-      case 8: return SmallDual<MM, 8>::lds_bytes(Q, kp, waves);
-      case 16: return SmallDual<MM, 16>::lds_bytes(Q, kp, waves);
-      case 32: return SmallDual<MM, 32>::lds_bytes(Q, kp, waves);
-      default: return SmallDual<MM, 64>::lds_bytes(Q, kp, waves);
+      case 8: return NC<MM, 8>::lds_bytes(Q, kp, waves);
+      case 16: return NC<MM, 16>::lds_bytes(Q, kp, waves);
+      case 32: return NC<MM, 32>::lds_bytes(Q, kp, waves);
+      default: return NC<MM, 64>::lds_bytes(Q, kp, waves);
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  if (M == 3) return f(std::integral_constant<int, 3>{});
+  return f(std::integral_constant<int, 4>{});
+}
+
+// basis-table columns the Newton kernel's Hessian segments read
+int dual_table_columns(int M, int NP) {
+  auto f = [&](auto tag) -> int {
+    constexpr int MM = decltype(tag)::value;
+    switch (NP) {
+      case 8: return NC<MM, 8>::KCOL;
+      case 16: return NC<MM, 16>::KCOL;
+      case 32: return NC<MM, 32>::KCOL;
+      default: return NC<MM, 64>::KCOL;
     }
   };
   if (M == 1) return f(std::integral_constant<int, 1>{});
@@ -158,8 +182,8 @@ Problem* get(ipm_ctx* ctx, int id) {
 
 void free_problem(Problem* P) {
   if (!P) return;
-  void* ptrs[] = {P->d_phi, P->d_wphi, P->d_u[0], P->d_u[1], P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res, P->d_cellN, P->d_ctrl};
+  void* ptrs[] = {P->d_phi,   P->d_wphi,  P->d_u[0], P->d_u[1],  P->d_lam,   P->d_nodal,
+                  P->d_ghost, P->d_res,   P->d_blk,  P->d_lists, P->d_cellN, P->d_ctrl};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -172,28 +196,32 @@ ipm_status plan(ipm_ctx* ctx, Problem& P) {
                 "m*N = " + std::to_string(n) + " unknowns per cell exceeds 64 (supported range of the "
                 "fused dual kernel)");
   P.NP = pow2_at_least(n, 8);
-  P.kp = std::max(P.N, (P.NP + P.M - 1) / P.M);
-  int waves = 4;
-  while (waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, waves) > 64 * 1024) waves >>= 1;
-  P.dual_waves = waves;
-  P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, waves);
+  P.kp = std::max(P.N, dual_table_columns(P.M, P.NP));
+  P.dual_waves = 4;
+  while (P.dual_waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves) > 64 * 1024)
+    P.dual_waves >>= 1;
+  P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves);
   if (P.dual_lds > ctx->max_lds)
     return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
                                     std::to_string(P.Q) + ")");
-  const int cpb = waves * (64 / P.NP);
-  P.dual_blocks = (P.cells + cpb - 1) / cpb;
   P.UG = pow2_at_least(std::min(64, std::max(P.Q, n)), 16);
   const int ucpb = 4 * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
   P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
-                                static_cast<size_t>(ucpb) * P.Q * P.M + 256);
+                                2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256);
+  // list l receives the routed cells of update blocks b = l (mod 64)
+  P.list_cap = ((P.upd_blocks + kSlots - 1) / kSlots) * ucpb;
+  // one Newton block per list entry (time steps) or per cell (setup, one-shot)
+  P.dual_blocks = std::max(kSlots * P.list_cap, P.cells);
   if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
   return IPM_OK;
 }
 
 DualParams dual_params(const Problem& P, int mode, int parity, const double* uhat, double* lam,
-                       double* nodal, int cells, const int8_t* cellN, StepCtrl* ctrl) {
+                       double* nodal, int cells, const int8_t* cellN, StepCtrl* ctrl,
+                       unsigned long long* blk) {
   DualParams d{};
+  d.blk_stats = blk;
   d.phi = P.d_phi;
   d.wphi = P.d_wphi;
   d.N = P.N;
@@ -215,11 +243,14 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   return d;
 }
 
+// Newton kernel over all cells in order (setup, one-shot) or over the
+// screened lists (d.list_cap > 0)
 ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int cells) {
   DualFn fn = pick_dual(P.M, P.NP);
   if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-  const int cpb = P.dual_waves * (64 / P.NP);
-  const int blocks = (cells + cpb - 1) / cpb;
+  const int per_block = P.dual_waves * (64 / P.NP);
+  const int items = d.list_cap > 0 ? kSlots * d.list_cap : cells;
+  const int blocks = (items + per_block - 1) / per_block;
   if (blocks == 0) return IPM_OK;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * P.dual_waves), P.dual_lds, ctx->stream, d);
   HIPCHK(ctx, hipGetLastError());
@@ -229,7 +260,11 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int 
 ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   const int parity = static_cast<int>(P.step_index & 1);
   DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
-                             P.d_cellN, P.d_ctrl);
+                             P.d_cellN, P.d_ctrl, P.d_blk);
+  if (!P.one_shot) {
+    d.lists = P.d_lists + static_cast<size_t>(parity) * kSlots * P.list_cap;
+    d.list_cap = P.list_cap;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
   if (ctx->timing) {
     while (ctx->ev.size() < ctx->ev_used + 4) {
@@ -273,14 +308,31 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   u.dy = P.dy;
   u.vol = P.vol;
   u.t_end = P.t_end;
-  u.steady_eps = P.steady_eps;
   u.ctrl = P.d_ctrl;
   u.parity = parity;
+  u.tau = P.tau;
+  u.one_shot = P.one_shot;
+  u.lists = P.d_lists + static_cast<size_t>(parity ^ 1) * kSlots * P.list_cap;
+  u.list_cap = P.list_cap;
   UpdFn fn = pick_update(P.M, P.UG);
   hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(256), P.upd_lds, ctx->stream, u);
   HIPCHK(ctx, hipGetLastError());
   if (ctx->timing) HIPCHK(ctx, hipEventRecord(e3, ctx->stream));
+  if (P.steady_eps > 0.0) {
+    hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
+                       P.upd_blocks, P.steady_eps, parity, P.d_blk, P.dual_blocks, 0);
+    HIPCHK(ctx, hipGetLastError());
+  }
   ++P.step_index;
+  return IPM_OK;
+}
+
+// residual of the last step and the Newton totals into the control block
+ipm_status enqueue_close(ipm_ctx* ctx, Problem& P) {
+  hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
+                     P.upd_blocks, P.steady_eps, static_cast<int>(P.step_index & 1), P.d_blk,
+                     P.dual_blocks, 1);
+  HIPCHK(ctx, hipGetLastError());
   return IPM_OK;
 }
 
@@ -297,6 +349,7 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
     for (int G : {16, 32, 64})
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
+
   (void)hipGetLastError();  // the request is best effort; do not leave a sticky error
   done = true;
   return IPM_OK;
@@ -395,7 +448,7 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
   const size_t n = static_cast<size_t>(M) * N;
   return sizeof(double) * (3 * cells * n + cells * Q * M + 2 * static_cast<size_t>(Q) * (N + 64) +
                            4 * static_cast<size_t>(Q) * M + cells / 8 + 64) +
-         cells + sizeof(StepCtrl);
+         cells + 2 * cells * sizeof(int) + sizeof(StepCtrl);
 }
 
 ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
@@ -411,13 +464,7 @@ ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
   ctx->max_problems = cfg->max_problems > 0 ? cfg->max_problems : 1024;
   e = hipSetDevice(cfg->device);
   if (e != hipSuccess) return fail(nullptr, IPM_E_DEVICE, hipGetErrorString(e));
-  if (cfg->hip_stream) {
-    ctx->stream = static_cast<hipStream_t>(cfg->hip_stream);
-  } else {
-    e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail(nullptr, IPM_E_DEVICE, hipGetErrorString(e));
-    ctx->own_stream = true;
-  }
+  ctx->stream = static_cast<hipStream_t>(cfg->hip_stream);  // NULL: the null stream
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, cfg->device) ==
           hipSuccess &&
@@ -535,6 +582,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   ALLOC(P.d_nodal, nod * sizeof(double));
   ALLOC(P.d_ghost, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double));
   ALLOC(P.d_res, static_cast<size_t>(P.upd_blocks) * sizeof(double));
+  ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long));
+  ALLOC(P.d_lists, 2 * static_cast<size_t>(kSlots) * P.list_cap * sizeof(int));
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
   if (P.uneven) ALLOC(P.d_cellN, static_cast<size_t>(P.cells));
 #undef ALLOC
@@ -550,6 +599,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   if (P.uneven)
     CHK(hipMemcpyAsync(P.d_cellN, cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  CHK(hipMemsetAsync(P.d_blk, 0, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long), s));
+  CHK(hipMemsetAsync(P.d_res, 0, static_cast<size_t>(P.upd_blocks) * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_ghost, 0, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_nodal, 0, nod * sizeof(double), s));
 
@@ -586,7 +637,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   }
   // converge the initial dual (setup mode of the dual kernel)
   {
-    DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN, P.d_ctrl);
+    DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN, P.d_ctrl,
+                               P.d_blk);
     st = launch_dual(ctx, P, d, P.cells);
     if (st != IPM_OK) return cleanup(st);
   }
@@ -602,6 +654,9 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
       std::memcpy(&gin[k * gq], pb->dirichlet + dsides[k] * gq, gq * sizeof(double));
     double *d_gin = nullptr, *d_gu = nullptr, *d_gl = nullptr, *d_gn = nullptr;
     StepCtrl* d_gc = nullptr;
+    unsigned long long* d_gb = nullptr;
+    CHK(hipMalloc(&d_gb, 64 * sizeof(unsigned long long)));
+    CHK(hipMemsetAsync(d_gb, 0, 64 * sizeof(unsigned long long), s));
     CHK(hipMalloc(&d_gin, gin.size() * sizeof(double)));
     CHK(hipMalloc(&d_gu, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
     CHK(hipMalloc(&d_gl, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
@@ -620,12 +675,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     gp.status = &d_gc->setup_status;
     hipLaunchKernelGGL(pick_setup(P.M), dim3(1), dim3(256), 0, s, gp);
     CHK(hipGetLastError());
-    DualParams d1 = dual_params(P, 1, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc);
+    DualParams d1 = dual_params(P, 1, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc, d_gb);
     st = launch_dual(ctx, P, d1, nd);
-    if (st != IPM_OK) return cleanup(st);
-    DualParams d0 = dual_params(P, 0, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc);
-    d0.one_shot = 0;
-    st = launch_dual(ctx, P, d0, nd);
     if (st != IPM_OK) return cleanup(st);
     for (int k = 0; k < nd; ++k)
       CHK(hipMemcpyAsync(P.d_ghost + dsides[k] * gq, d_gn + k * gq, gq * sizeof(double),
@@ -638,11 +689,12 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     (void)hipFree(d_gl);
     (void)hipFree(d_gn);
     (void)hipFree(d_gc);
+    (void)hipFree(d_gb);
     if (gc.setup_status || gc.status)
       return cleanup(fail(ctx, IPM_E_REALIZABILITY, "Dirichlet ghost state has no admissible dual"));
-    for (int k = 0; k < 64; ++k) {
-      gax = std::max(gax, __builtin_bit_cast(double, gc.amax[0][0][k]));
-      gay = std::max(gay, __builtin_bit_cast(double, gc.amax[0][1][k]));
+    for (int k = 0; k < kSlots; ++k) {
+      gax = std::max(gax, __builtin_bit_cast(double, gc.amax[0][0][k * kSlotStride]));
+      gay = std::max(gay, __builtin_bit_cast(double, gc.amax[0][1][k * kSlotStride]));
     }
   }
   StepCtrl hc;
@@ -657,10 +709,11 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     return cleanup(fail(ctx, hc.setup_status & kStRealizability ? IPM_E_REALIZABILITY : IPM_E_NEWTON,
                         why + " (status " + std::to_string(hc.setup_status) + ")"));
   }
-  std::memset(&hc, 0, sizeof(hc));
-  hc.ghost_amax[0] = gax;
-  hc.ghost_amax[1] = gay;
-  CHK(hipMemcpyAsync(P.d_ctrl, &hc, sizeof(StepCtrl), hipMemcpyHostToDevice, s));
+  // keep the speed slots of the converged initial state (the first step of
+  // the classical mode starts there); one-shot recomputes every cell's ansatz
+  if (P.one_shot) CHK(hipMemsetAsync(&P.d_ctrl->amax[0][0][0], 0, sizeof(P.d_ctrl->amax[0]), s));
+  const double gam[2] = {gax, gay};
+  CHK(hipMemcpyAsync(&P.d_ctrl->ghost_amax[0], gam, sizeof(gam), hipMemcpyHostToDevice, s));
   CHK(hipStreamSynchronize(s));
 #undef CHK
   ctx->used += P.bytes;
@@ -681,6 +734,11 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
       ipm_status st = enqueue_step(ctx, *get(ctx, ids[k]));
       if (st != IPM_OK) return st;
     }
+  if (max_steps > 0)
+    for (int k = 0; k < n_ids; ++k) {
+      ipm_status st = enqueue_close(ctx, *get(ctx, ids[k]));
+      if (st != IPM_OK) return st;
+    }
   if (info)
     for (int k = 0; k < n_ids; ++k) {
       ipm_status st = ipm_query(ctx, ids[k], &info[k]);
@@ -696,7 +754,7 @@ ipm_status ipm_query(ipm_ctx* ctx, int id, ipm_step_info* info) {
   StepCtrl hc;
   HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  info->done = hc.done;
+  info->done = (hc.done[hc.steps & 1] || hc.status) ? 1 : 0;
   info->steps = static_cast<long long>(hc.steps);
   info->t = hc.t[hc.steps & 1];
   info->dt = hc.dt_last;

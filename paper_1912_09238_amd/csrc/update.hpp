@@ -1,17 +1,29 @@
 // Kinetic flux and moment update (Sec. 3.1 eq:momentIterationFunction in
-// the quadrature form eq:momentUpQuadrature; Sec. 3.2), the time step, the
-// steady residual eq:residualSteady and the per-step bookkeeping.
+// the quadrature form eq:momentUpQuadrature; Sec. 3.2), the time step and
+// the steady residual eq:residualSteady.
 //
 // A group of G lanes owns one cell.  Lanes over quadrature nodes read the
 // nodal ansatz of the cell and its neighbours (written by the dual kernel),
-// apply the deterministic numerical flux per node and form the nodal
-// update u - dt/dx (g_r - g_l) [- dt/dy (g_n - g_s)] in LDS; lanes over
-// moments then project it on the basis.  The old-moment term is the ansatz
-// h(lambda_c) itself, as in eq:momentIterationFunction.  The last block to
-// finish closes the step: time, residual (fixed summation order), done flag.
+// apply the deterministic numerical flux per node and form the nodal update
+// u - dt/dx (g_r - g_l) [- dt/dy (g_n - g_s)] in LDS; lanes over moments then
+// project it on the basis.  The old-moment term is the ansatz h(lambda_c)
+// itself, as in eq:momentIterationFunction.
+//
+// The same kernel takes the tau test of the next time step at its warm
+// start: with lambda^n unchanged, the dual gradient is h(lambda^n) - uhat^{n+1}
+// = <u_s(lambda^n . phi) phi>_Q - uhat^{n+1}, and both terms are at hand.
+// Cells whose residual is clearly below tau (below tau/2, so rounding of
+// this shortcut cannot change the outcome of the test) keep their dual and
+// nodal ansatz, and their wave speeds enter the next step's slots here;
+// the others are appended to the next step's Newton lists.
+//
+// Step bookkeeping avoids device-scope fences: every block derives the same
+// dt from the 64 speed slots; block 0 alone advances t, the step count and
+// the stop flag of the next step parity; the residual is written as one
+// partial per block and reduced in fixed order by a one-block kernel.
 #pragma once
 
-#include "dual_small.hpp"
+#include "dual.hpp"
 
 namespace ipm {
 
@@ -26,7 +38,11 @@ struct UpdateParams {
   double* __restrict__ res_part;     // [gridDim.x]
   int bc[4];
   int flux;
-  double gamma, cfl, dx, dy, vol, t_end, steady_eps;
+  double gamma, cfl, dx, dy, vol, t_end;
+  double tau;
+  int one_shot;
+  int* __restrict__ lists;           // [64][list_cap] Newton lists of the next step
+  int list_cap;
   StepCtrl* ctrl;
   int parity;
 };
@@ -54,28 +70,52 @@ __device__ __forceinline__ const double* neighbour_nodal(const UpdateParams& P, 
   return P.nodal + (static_cast<size_t>(jy) * P.nx + jx) * P.Q * M;
 }
 
+// largest wave speeds of the step: the first wavefront reads the 64 slots,
+// one per lane, and reduces them; the result is shared through LDS.
+__device__ __forceinline__ void step_speeds(const StepCtrl* C, int parity, int dim, double& ax,
+                                            double& ay, double* sh) {
+  if (threadIdx.x < 64) {
+    const int s = threadIdx.x;
+    double vx = __longlong_as_double(static_cast<long long>(C->amax[parity][0][s * kSlotStride]));
+    double vy = dim == 2 ? __longlong_as_double(
+                               static_cast<long long>(C->amax[parity][1][s * kSlotStride]))
+                         : 0.0;
+    vx = wave_max(vx);
+    vy = wave_max(vy);
+    if (threadIdx.x == 0) {
+      sh[0] = nan_max(vx, C->ghost_amax[0]);
+      sh[1] = nan_max(vy, C->ghost_amax[1]);
+    }
+  }
+  __syncthreads();
+  ax = sh[0];
+  ay = sh[1];
+}
+
 template <int M, int G>
 __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
   StepCtrl* C = P.ctrl;
-  if (C->done) return;
+  if (C->done[P.parity] || C->status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      C->done[P.parity ^ 1] = 1;
+      C->t[P.parity ^ 1] = C->t[P.parity];
+    }
+    return;
+  }
   extern __shared__ double smem[];
   const int Q = P.Q, kp = P.kp, N = P.N;
   double* wphiL = smem;
   for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) wphiL[k] = P.wphi[k];
   constexpr int CPW = 64 / G;
   const int groups = (blockDim.x >> 6) * CPW;
-  double* UT = wphiL + Q * kp;  // per group [Q][M]
-  double* red = UT + static_cast<size_t>(groups) * Q * M;
-  __shared__ int s_last;
+  double* UT = wphiL + Q * kp;                           // per group [Q][M] updated nodes
+  double* UC = UT + static_cast<size_t>(groups) * Q * M;  // per group [Q][M] current nodes
+  double* red = UC + static_cast<size_t>(groups) * Q * M;
 
-  // time step from the largest wave speed of this step's ansatz (all cells,
-  // all nodes, Dirichlet ghosts)
-  double ax = C->ghost_amax[0], ay = C->ghost_amax[1];
-  for (int s = 0; s < 64; ++s) {
-    ax = nan_max(ax, __longlong_as_double(static_cast<long long>(C->amax[P.parity][0][s])));
-    if (P.dim == 2)
-      ay = nan_max(ay, __longlong_as_double(static_cast<long long>(C->amax[P.parity][1][s])));
-  }
+  __shared__ double sh_speed[2];
+  __shared__ int s_route[16];
+  double ax, ay;
+  step_speeds(C, P.parity, P.dim, ax, ay, sh_speed);
   const double t0 = C->t[P.parity];
   double dt = P.dim == 2 ? P.cfl / (ax / P.dx + ay / P.dy) : P.cfl * P.dx / ax;
   bool last = false;
@@ -84,15 +124,15 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
     last = true;
   }
   const double lfx = P.dx / (2.0 * dt), lfy = P.dy / (2.0 * dt);
-  __syncthreads();
 
   const int lane = threadIdx.x & 63;
   const int gid = (threadIdx.x >> 6) * CPW + lane / G;
   const int r = lane % G;
   const int cell = blockIdx.x * groups + gid;
   double* ut = UT + static_cast<size_t>(gid) * Q * M;
-  double res_cell = 0.0;
-  int finite = 1;
+  double* uq = UC + static_cast<size_t>(gid) * Q * M;
+  double res_cell = 0.0, nx_speed = 0.0, ny_speed = 0.0;
+  int finite = 1, route = 0;
   if (cell < P.cells) {
     const int ix = cell % P.nx, iy = cell / P.nx;
     const double* uc = P.nodal + static_cast<size_t>(cell) * Q * M;
@@ -104,92 +144,168 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
     for (int q = r; q < Q; q += G) {
       double c[M], l[M], rr[M], gl[M], gr[M], acc[M];
 #pragma unroll
-      for (int a = 0; a < M; ++a) {
-        c[a] = uc[q * M + a];
-        l[a] = uw[q * M + a];
-        rr[a] = ue[q * M + a];
+      for (int b = 0; b < M; ++b) {
+        c[b] = uc[q * M + b];
+        l[b] = uw[q * M + b];
+        rr[b] = ue[q * M + b];
       }
       numerical_flux<M>(P.flux, P.gamma, 0, c, rr, lfx, gr);
       numerical_flux<M>(P.flux, P.gamma, 0, l, c, lfx, gl);
 #pragma unroll
-      for (int a = 0; a < M; ++a) acc[a] = c[a] - rx * (gr[a] - gl[a]);
+      for (int b = 0; b < M; ++b) acc[b] = c[b] - rx * (gr[b] - gl[b]);
       if (P.dim == 2) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-          l[a] = us[q * M + a];
-          rr[a] = un[q * M + a];
+        for (int b = 0; b < M; ++b) {
+          l[b] = us[q * M + b];
+          rr[b] = un[q * M + b];
         }
         numerical_flux<M>(P.flux, P.gamma, 1, c, rr, lfy, gr);
         numerical_flux<M>(P.flux, P.gamma, 1, l, c, lfy, gl);
 #pragma unroll
-        for (int a = 0; a < M; ++a) acc[a] -= ry * (gr[a] - gl[a]);
+        for (int b = 0; b < M; ++b) acc[b] -= ry * (gr[b] - gl[b]);
       }
 #pragma unroll
-      for (int a = 0; a < M; ++a) ut[q * M + a] = acc[a];
+      for (int b = 0; b < M; ++b) {
+        ut[q * M + b] = acc[b];
+        uq[q * M + b] = c[b];
+      }
+      if (!P.one_shot) {
+        double sx, sy;
+        wave_speeds<M>(P.gamma, P.dim, c, sx, sy);
+        nx_speed = nan_max(nx_speed, sx);
+        ny_speed = nan_max(ny_speed, sy);
+      }
     }
     wave_sync();
     const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
-    double d2 = 0.0;
+    double d2 = 0.0, gsq[M];
+#pragma unroll
+    for (int b = 0; b < M; ++b) gsq[b] = 0.0;
     for (int k = r; k < M * N; k += G) {
-      const int a = k / N, i = k % N;
-      double s = 0.0;
+      const int b = k / N, i = k % N;
+      double v = 0.0, h = 0.0;
       if (i < Nc)
-        for (int q = 0; q < Q; ++q) s = fma(ut[q * M + a], wphiL[q * kp + i], s);
+        for (int q = 0; q < Q; ++q) {
+          const double w = wphiL[q * kp + i];
+          v = fma(ut[q * M + b], w, v);
+          h = fma(uq[q * M + b], w, h);
+        }
       const size_t off = static_cast<size_t>(cell) * M * N + k;
-      const double d = s - P.uold[off];
+      const double d = v - P.uold[off];
       d2 = fma(d, d, d2);
-      finite &= (s == s && fabs(s) < 1e300) ? 1 : 0;
-      P.unew[off] = s;
+      finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
+      P.unew[off] = v;
+      const double g = h - v;  // next step's dual gradient at its warm start
+#pragma unroll
+      for (int bb = 0; bb < M; ++bb) gsq[bb] += (bb == b) ? g * g : 0.0;
     }
     d2 = group_sum<G>(d2);
     res_cell = P.vol * sqrt(d2);
+    if (!P.one_shot) {
+      double resn = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) resn += sqrt(group_sum<G>(gsq[b]));
+      route = (resn < 0.5 * P.tau) ? 0 : 1;  // NaN routes to Newton, which reports it
+    }
   }
-  finite = group_and<G>(finite);
+  // speeds of the cells whose nodal ansatz carries over to the next step
+  nx_speed = route ? 0.0 : nx_speed;
+  ny_speed = route ? 0.0 : ny_speed;
+  nx_speed = wave_max(nx_speed);
+  ny_speed = wave_max(ny_speed);
+  finite = __ballot(!finite) == 0ull ? 1 : 0;
   // fixed-order block partial of the residual
   if (r == 0) {
     red[2 * gid] = res_cell;
     red[2 * gid + 1] = finite ? 0.0 : 1.0;
+    s_route[gid] = (cell < P.cells) ? route : 0;
+  }
+  if (lane == 0) {
+    red[2 * groups + 2 * (threadIdx.x >> 6)] = nx_speed;
+    red[2 * groups + 2 * (threadIdx.x >> 6) + 1] = ny_speed;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0, bad = 0.0;
+    double sres = 0.0, bad = 0.0;
+    int cnt = 0;
     for (int k = 0; k < groups; ++k) {
-      s += red[2 * k];
+      sres += red[2 * k];
       bad += red[2 * k + 1];
+      cnt += s_route[k];
     }
-    P.res_part[blockIdx.x] = s;
-    if (bad > 0.0 || !(ax == ax) || !(ay == ay) || !(dt > 0.0 || last)) atomicOr(&C->status, kStNonfinite);
-    __threadfence();
-    const unsigned prev = atomicAdd(&C->blocks_done, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    P.res_part[blockIdx.x] = sres;
+    if (bad > 0.0 || !(ax == ax) || !(ay == ay) || !(dt > 0.0 || last))
+      atomicOr(&C->status, kStNonfinite);
+    const int slot = blockIdx.x & (kSlots - 1);
+    if (!P.one_shot) {
+      double mx = 0.0, my = 0.0;
+      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+        mx = nan_max(mx, red[2 * groups + 2 * w]);
+        my = nan_max(my, red[2 * groups + 2 * w + 1]);
+      }
+      atomicMax(&C->amax[P.parity ^ 1][0][slot * kSlotStride], speed_bits(mx));
+      if (P.dim == 2) atomicMax(&C->amax[P.parity ^ 1][1][slot * kSlotStride], speed_bits(my));
+      int base = cnt ? static_cast<int>(atomicAdd(
+                           &C->list_len[(P.parity ^ 1) * kSlots * kSlotStride + slot * kSlotStride],
+                           static_cast<unsigned>(cnt)))
+                     : 0;
+      for (int k = 0; k < groups; ++k)
+        if (s_route[k]) {
+          if (base < P.list_cap)
+            P.lists[static_cast<size_t>(slot) * P.list_cap + base] = blockIdx.x * groups + k;
+          ++base;
+        }
+    }
+    if (blockIdx.x == 0) {
+      C->t[P.parity ^ 1] = last ? P.t_end : t0 + dt;
+      C->done[P.parity ^ 1] = last ? 1 : 0;
+      C->dt_last = dt;
+      C->amax_last = P.dim == 2 ? nan_max(ax, ay) : ax;
+      C->steps += 1;
+    }
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // last block: residual in fixed order, then close the step
-  const volatile double* rp = P.res_part;
+}
+
+// One block: residual of the last update (fixed summation order) and, for
+// steady problems, the stop test eq:residualSteady <= eps.  Also folds the
+// per-block Newton counters into the control block when `close` is set.
+__global__ __launch_bounds__(256) void residual_kernel(StepCtrl* C, const double* res_part,
+                                                       int nparts, double steady_eps, int parity,
+                                                       const unsigned long long* blk_stats,
+                                                       int nblk, int close) {
+  __shared__ double red[256];
+  __shared__ unsigned long long rit[256];
+  __shared__ unsigned long long rmx[256];
   double s = 0.0;
-  for (int k = threadIdx.x; k < static_cast<int>(gridDim.x); k += blockDim.x) s += rp[k];
+  for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += res_part[k];
   red[threadIdx.x] = s;
+  unsigned long long it = 0, mx = 0;
+  if (close)
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+      it += blk_stats[2 * k];
+      mx = blk_stats[2 * k + 1] > mx ? blk_stats[2 * k + 1] : mx;
+    }
+  rit[threadIdx.x] = it;
+  rmx[threadIdx.x] = mx;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (static_cast<int>(threadIdx.x) < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      rit[threadIdx.x] += rit[threadIdx.x + w];
+      rmx[threadIdx.x] = rmx[threadIdx.x] > rmx[threadIdx.x + w] ? rmx[threadIdx.x]
+                                                                  : rmx[threadIdx.x + w];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double residual = red[0];
-    C->t[P.parity ^ 1] = last ? P.t_end : t0 + dt;
-    C->dt_last = dt;
-    C->residual = residual;
-    C->amax_last = P.dim == 2 ? nan_max(ax, ay) : ax;
-    C->steps += 1;
-    for (int k = 0; k < 64; ++k) {
-      C->amax[P.parity ^ 1][0][k] = 0ull;
-      C->amax[P.parity ^ 1][1][k] = 0ull;
+    if (C->steps > 0) C->residual = red[0];
+    if (!close && !C->done[parity] && !C->status && steady_eps > 0.0 && C->steps > 0 &&
+        red[0] <= steady_eps)
+      C->done[parity ^ 1] = 1;
+    if (close) {
+      C->newton_iters = rit[0];
+      C->max_iters = static_cast<unsigned>(rmx[0]);
     }
-    C->blocks_done = 0u;
-    const unsigned st = atomicOr(&C->status, 0u);
-    if (last || (P.steady_eps > 0.0 && residual <= P.steady_eps) || st != 0u) C->done = 1;
   }
 }
 
