@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--trajectory-steps", type=int, default=0,
+                    help="steps of one full trajectory if known (skips probing it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -94,15 +96,18 @@ def main():
     cells = spec["nx"]
 
     # trajectory length (untimed; also warms the kernels)
-    pid = ctx.set_problem(spec, ic_nodal=ic)
-    while True:
-        ctx.step(pid, 512)
-        traj = ctx.query(pid)
-        if traj["done"]:
-            break
-    L = traj["steps"]
-    assert traj["status"] == 0 and traj["done"], traj
-    ctx.release(pid)
+    if args.trajectory_steps > 0:
+        L = args.trajectory_steps
+    else:
+        pid = ctx.set_problem(spec, ic_nodal=ic)
+        while True:
+            ctx.step(pid, 512)
+            traj = ctx.query(pid)
+            if traj["done"]:
+                break
+        L = traj["steps"]
+        assert traj["status"] == 0 and traj["done"], traj
+        ctx.release(pid)
 
     def fresh_instances(total):
         k = max(1, -(-total // L))

@@ -30,6 +30,8 @@
 // on separate cache lines; no device-scope fence is issued.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace ipm {
@@ -92,6 +94,33 @@ __device__ __forceinline__ double dpp_mov(double v) {
   const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
+}
+
+// Broadcast lane N of each 16-lane row to the whole row (64-bit row_newbcast DPP).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long x = __builtin_amdgcn_update_dpp(0ll, __builtin_bit_cast(long long, v), 0x150 + N,
+                                                  0xF, 0xF, true);
+  return __builtin_bit_cast(double, x);
+}
+
+// For aligned 32-lane groups: lo holds the group's lanes 0..15 in both of its
+// 16-lane rows, hi its lanes 16..31 (v_permlane16_swap on each 32-bit half).
+__device__ __forceinline__ void group32_halves(double v, double& lo, double& hi) {
+  const int a = __double2loint(v), b = __double2hiint(v);
+  const auto pa = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+  const auto pb = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+  lo = __hiloint2double(pb[0], pa[0]);
+  hi = __hiloint2double(pb[1], pa[1]);
+}
+
+// Compile-time loop: f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -184,20 +213,28 @@ __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lam
 
 // ---------------------------------------------------------------- Newton
 
-// Layout: a group of G = NP lanes owns one cell, 64/NP cells per wavefront,
-// four wavefronts per block.  Lane r of a group holds row r of the Hessian
-// (all NP columns) and the unknown r.  Control flow is uniform within a
-// group; groups of one wavefront may leave the Newton loop at different
-// iterations (all cross-lane operations stay inside the group).
+// Layout: a group of G = NP / R lanes owns one cell, 64 / G cells per
+// wavefront, up to four wavefronts per block.  Lane r of a group holds the R
+// Hessian rows r, r + G, ... (all NP columns each) and the matching unknowns.
+// With R = 2 every pivot-column value read from LDS feeds two rows, which
+// halves the LDS traffic of the elimination (the kernel is LDS-bound).
+// Control flow is uniform within a group; groups of one wavefront may leave
+// the Newton loop at different iterations (cross-lane operations stay inside
+// the group).
 template <int M, int NP>
 struct NewtonCfg {
-  static constexpr int G = NP;
-  static constexpr int CPW = 64 / NP;
+  // NP = 16, 32: the elimination broadcasts pivot columns register to
+  // register (DPP row broadcast, plus a 16-lane row swap for 32-lane
+  // groups); otherwise through LDS.
+  static constexpr bool kDpp = (NP == 16 || NP == 32);
+  static constexpr int R = 1;
+  static constexpr int G = NP / R;
+  static constexpr int CPW = 64 / G;
   static constexpr int NJ = M * (M + 1) / 2;
   static constexpr int KCOL = (NP + M - 1) / M;  // table columns the rows read
 
   __host__ __device__ static int group_doubles(int Q) {
-    return NP + Q * (M + NJ) + 2 * NP + 2 + NP;
+    return NP + Q * (M + NJ) + (kDpp ? 0 : 2 * NP + 2 + NP);
   }
   __host__ __device__ static size_t lds_bytes(int Q, int kp, int waves) {
     // tables, per-group work areas, then 2 stats per group + 2 speeds per wave
@@ -207,10 +244,15 @@ struct NewtonCfg {
   }
 };
 
+// Read-only table through the scalar unit: the basis values of one node are
+// the same for every lane, so they need not occupy LDS bandwidth.
+typedef const __attribute__((address_space(4))) double* const_dptr;
+
 template <int M, int NP>
 __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
   using Cfg = NewtonCfg<M, NP>;
-  constexpr int G = Cfg::G, CPW = Cfg::CPW, NJ = Cfg::NJ;
+  constexpr int G = Cfg::G, CPW = Cfg::CPW, NJ = Cfg::NJ, R = Cfg::R;
+  constexpr bool kDpp = Cfg::kDpp;
   if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
   if (P.mode == 0 && blockIdx.x == 0) {
     // the flux update of this step fills the next step's speed slots and list
@@ -247,15 +289,24 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
     phiL[k] = P.phi[k];
     wphiL[k] = P.wphi[k];
   }
+  const const_dptr phiC = (const_dptr)(P.phi);
   const int gidx_l = wave * CPW + grp;
   double* lamS = wphiL + Q * kp + static_cast<size_t>(gidx_l) * Cfg::group_doubles(Q);  // [NP]
   double* US = lamS + NP;         // [Q][M]
   double* JS = US + Q * M;        // [Q][NJ]
-  double* cA = JS + Q * NJ;       // [2][NP] pivot column
+  double* cA = JS + Q * NJ;       // [2][NP] pivot column (LDS elimination)
   double* cX = cA + 2 * NP;       // [2] pivot row's right-hand side
   double* cP = cX + 2;            // [NP] pivots
   double* stats = wphiL + Q * kp + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
   __syncthreads();
+
+  // elimination steps the wavefront runs: the largest unknown count of its
+  // cells (wave-uniform, so each step is a scalar branch; smaller cells see
+  // only identity rows in the extra steps)
+  const int nc_lane = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) * M : 0;
+  const int kmax =
+      __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max(static_cast<double>(nc_lane))));
+  (void)kmax;
 
   int its = 0;
   unsigned status = 0;
@@ -263,13 +314,22 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
   if (cell >= 0) {
     const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
     const int nc = Nc * M;
-    const int i = r / M, a = r % M;
-    const bool live = r < nc;
-    const size_t gidx = static_cast<size_t>(cell) * M * N + static_cast<size_t>(a) * N + i;
-    double lam_r = live ? P.lam[gidx] : 0.0;
-    const double uh_r = live ? P.uhat[gidx] : 0.0;
-
-    lamS[r] = lam_r;
+    // unknown (i, a) of row ro = i * M + a; rows r + s * G of this lane
+    int ro[R], ii[R], aa[R];
+    bool live[R];
+    size_t gidx[R];
+    double lam[R], uh[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      ro[s] = r + s * G;
+      ii[s] = ro[s] / M;
+      aa[s] = ro[s] % M;
+      live[s] = ro[s] < nc;
+      gidx[s] = static_cast<size_t>(cell) * M * N + static_cast<size_t>(aa[s]) * N + ii[s];
+      lam[s] = live[s] ? P.lam[gidx[s]] : 0.0;
+      uh[s] = live[s] ? P.uhat[gidx[s]] : 0.0;
+      lamS[ro[s]] = lam[s];
+    }
     wave_sync();
     double ssum = 0.0;
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
@@ -277,22 +337,33 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
     int ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, r, G, US, JS, ssum));
     wave_sync();
 
-    auto gradient = [&](double& g_out) -> double {
-      double g = 0.0;
-      if (live)
-        for (int q = 0; q < Q; ++q) g = fma(US[q * M + a], wphiL[q * kp + i], g);
-      g = live ? g - uh_r : 0.0;
-      g_out = g;
+    double g[R];
+    auto gradient = [&]() -> double {
+      double e2[M];
+#pragma unroll
+      for (int b = 0; b < M; ++b) e2[b] = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        double gs = 0.0;
+        if (live[s])
+          for (int q = 0; q < Q; ++q) gs = fma(US[q * M + aa[s]], wphiL[q * kp + ii[s]], gs);
+        gs = live[s] ? gs - uh[s] : 0.0;
+        g[s] = gs;
+#pragma unroll
+        for (int b = 0; b < M; ++b) e2[b] += (aa[s] == b) ? gs * gs : 0.0;
+      }
       // sum over variables of the Euclidean norm over modes (eq:tauCrit)
       double res = 0.0;
 #pragma unroll
-      for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>((a == b) ? g * g : 0.0));
+      for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(e2[b]));
       return res;
     };
 
-    double g_r = 0.0;
-    double res = ok ? gradient(g_r) : 0.0;
-    if (!ok) status |= kStRealizability;
+    double res = 0.0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) g[s] = 0.0;
+    if (ok) res = gradient();
+    else status |= kStRealizability;
 
     while (ok) {
       if (!(res == res) || res > 1e300) {
@@ -306,70 +377,168 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
           break;
         }
       }
-      // ---- Hessian row in registers; identity beyond the nc unknowns
-      double row[NP];
+      // ---- Hessian rows in registers; identity beyond the nc unknowns
+      double row[R][NP];
 #pragma unroll
-      for (int c = 0; c < NP; ++c) row[c] = 0.0;
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) row[s][c] = 0.0;
       {
-        const double live_f = live ? 1.0 : 0.0;
-        int aidx[M];
+        int aidx[R][M];
+        double live_f[R];
 #pragma unroll
-        for (int b = 0; b < M; ++b) aidx[b] = Packed<M>::idx(a, b);
+        for (int s = 0; s < R; ++s) {
+          live_f[s] = live[s] ? 1.0 : 0.0;
+#pragma unroll
+          for (int b = 0; b < M; ++b) aidx[s][b] = Packed<M>::idx(aa[s], b);
+        }
         for (int q = 0; q < Q; ++q) {
-          const double wi = wphiL[q * kp + i] * live_f;
           const double* Jq = JS + q * NJ;
-          double sb[M];
+          double sb[R][M];
 #pragma unroll
-          for (int b = 0; b < M; ++b) sb[b] = Jq[aidx[b]] * wi;
-          const double* ph = phiL + q * kp;  // same address in every lane: broadcast
+          for (int s = 0; s < R; ++s) {
+            const double wi = wphiL[q * kp + ii[s]] * live_f[s];
 #pragma unroll
-          for (int c = 0; c < NP; ++c) row[c] = fma(sb[c % M], ph[c / M], row[c]);
+            for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
+          }
+          const_dptr ph = phiC + q * kp;  // uniform: scalar loads
+#pragma unroll
+          for (int c = 0; c < NP; ++c) {
+            const double v = ph[c / M];
+#pragma unroll
+            for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
+          }
         }
 #pragma unroll
-        for (int c = 0; c < NP; ++c) row[c] = (live && c < nc) ? row[c] : (c == r ? 1.0 : 0.0);
+        for (int s = 0; s < R; ++s)
+#pragma unroll
+          for (int c = 0; c < NP; ++c)
+            row[s][c] = (live[s] && c < nc) ? row[s][c] : (c == ro[s] ? 1.0 : 0.0);
       }
-      // ---- Gauss-Jordan solve H d = g: the pivot row equals the pivot
-      // column in the symmetric Schur complement, one LDS broadcast per step
-      double x = g_r;
+      // ---- Gauss-Jordan solve H d = g without pivoting (H is SPD).  In the
+      // symmetric Schur complement the pivot row equals the pivot column, so
+      // a broadcast of the column serves all rows and the eliminated system
+      // needs no back-substitution.
+      double x[R], d[R];
       int pd_ok = 1;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        // steps beyond the cell's unknowns would only touch the identity
-        // block; skipping them also bounds the scheduler's window per step
-        if (k < nc) {
-          double* A = cA + (k & 1) * NP;
-          A[r] = row[k];
-          if (r == k) cX[k & 1] = x;
-          wave_sync();
-          const double piv = A[k];
-          const double gk = cX[k & 1];
-          pd_ok &= piv > 0.0 ? 1 : 0;
-          if (r == k) cP[k] = piv;
-          const double f = (r == k) ? 0.0 : row[k] * recip(piv);
-#pragma unroll
-          for (int j = k + 1; j < NP; ++j) row[j] = fma(-f, A[j], row[j]);
-          x = fma(-f, gk, x);
+      if constexpr (kDpp) {
+        // column entry j lives in lane j of the group; lanes 16..31 of a
+        // 32-lane group are reached through the swapped copy
+        auto halves = [&](double v, double& lo, double& hi) __attribute__((always_inline)) {
+          if constexpr (G == 32) {
+            group32_halves(v, lo, hi);
+          } else {
+            lo = v;
+            hi = v;
+          }
+        };
+        double dg = 1.0, xv = g[0];
+        static_for<0, NP>([&](auto kc) __attribute__((always_inline)) {
+          constexpr int k = decltype(kc)::value;
+          if (k < kmax) {
+            double clo, chi, xlo, xhi;
+            halves(row[0][k], clo, chi);
+            halves(xv, xlo, xhi);
+            const double piv = (k < 16) ? row_bcast<k % 16>(clo) : row_bcast<k % 16>(chi);
+            const double gk = (k < 16) ? row_bcast<k % 16>(xlo) : row_bcast<k % 16>(xhi);
+            pd_ok &= piv > 0.0 ? 1 : 0;
+            if (r == k) dg = piv;
+            const double f = (r == k) ? 0.0 : row[0][k] * recip(piv);
+            xv = fma(-f, gk, xv);
+            static_for<k + 1, NP>([&](auto jc) __attribute__((always_inline)) {
+              constexpr int j = decltype(jc)::value;
+              const double aj = (j < 16) ? row_bcast<j % 16>(clo) : row_bcast<j % 16>(chi);
+              row[0][j] = fma(-f, aj, row[0][j]);
+            });
+          }
+          // one step at a time: interleaving steps keeps every step's
+          // multipliers and broadcasts live at once
+          __builtin_amdgcn_sched_barrier(0);
+        });
+        if (!group_all(pd_ok)) {
+          status |= kStCholesky;
+          break;
         }
+        x[0] = xv;
+        d[0] = live[0] ? xv * recip(dg) : 0.0;
+      } else {
+        // LDS broadcast: the step reads the whole column in one batch,
+        // updates and publishes the next column first, then the rest of the
+        // row while that write lands
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          x[s] = g[s];
+          cA[ro[s]] = row[s][0];
+        }
+        if (r == 0) cX[0] = x[0];
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          // steps beyond the cell's unknowns would only touch the identity block
+          if (k < nc) {
+            const double* A = cA + (k & 1) * NP;
+            double* An = cA + ((k + 1) & 1) * NP;
+            double col[NP];
+#pragma unroll
+            for (int j = k; j < NP; ++j) col[j] = A[j];
+            const double gk = cX[k & 1];
+            const double piv = col[k];
+            pd_ok &= piv > 0.0 ? 1 : 0;
+            if (r == k % G) cP[k] = piv;
+            const double rp = recip(piv);
+            double f[R];
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+              f[s] = (ro[s] == k) ? 0.0 : row[s][k] * rp;
+              x[s] = fma(-f[s], gk, x[s]);
+            }
+            if (k + 1 < NP) {
+#pragma unroll
+              for (int s = 0; s < R; ++s) {
+                row[s][k + 1] = fma(-f[s], col[k + 1], row[s][k + 1]);
+                An[ro[s]] = row[s][k + 1];
+              }
+              if (r == (k + 1) % G) cX[(k + 1) & 1] = x[(k + 1) / G];
+            }
+#pragma unroll
+            for (int j = k + 2; j < NP; ++j)
+#pragma unroll
+              for (int s = 0; s < R; ++s) row[s][j] = fma(-f[s], col[j], row[s][j]);
+            wave_sync();
+          }
+        }
+        if (!group_all(pd_ok)) {
+          status |= kStCholesky;
+          break;
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < R; ++s) d[s] = live[s] ? x[s] * recip(cP[ro[s]]) : 0.0;
       }
-      if (!group_all(pd_ok)) {
-        status |= kStCholesky;
-        break;
-      }
-      wave_sync();
-      const double d_r = live ? x * recip(cP[r]) : 0.0;
       // ---- step length
       const bool ls = !P.one_shot && res > 1e-6;
       double L0 = 0.0, slope = 0.0;
       if (ls) {
-        L0 = group_sum<G>(ssum - lam_r * uh_r);
-        slope = group_sum<G>(g_r * d_r);
+        double l0 = ssum, sl = 0.0;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          l0 -= lam[s] * uh[s];
+          sl += g[s] * d[s];
+        }
+        L0 = group_sum<G>(l0);
+        slope = group_sum<G>(sl);
       }
-      double t = 1.0, lt_r = lam_r;
+      double t = 1.0, lt[R];
+#pragma unroll
+      for (int s = 0; s < R; ++s) lt[s] = lam[s];
       int accepted = 0;
 #pragma unroll 1
       for (int h = 0; h <= 60; ++h) {
-        lt_r = lam_r - t * d_r;
-        lamS[r] = lt_r;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          lt[s] = lam[s] - t * d[s];
+          lamS[ro[s]] = lt[s];
+        }
         wave_sync();
         ssum = 0.0;
         ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, r, G, US, JS, ssum));
@@ -379,7 +548,10 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
           break;
         }
         if (ok) {
-          const double Lt = group_sum<G>(ssum - lt_r * uh_r);
+          double lt_sum = ssum;
+#pragma unroll
+          for (int s = 0; s < R; ++s) lt_sum -= lt[s] * uh[s];
+          const double Lt = group_sum<G>(lt_sum);
           if (Lt <= L0 - 1e-4 * t * slope) {
             accepted = 1;
             break;
@@ -391,18 +563,21 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
         status |= kStLineSearch;
         break;
       }
-      lam_r = lt_r;
+#pragma unroll
+      for (int s = 0; s < R; ++s) lam[s] = lt[s];
       ++its;
       if (!ok) {
         status |= kStRealizability;
         break;
       }
-      res = gradient(g_r);
+      res = gradient();
       if (P.one_shot) break;
     }
 
     // ---- write back: dual, nodal ansatz, wave speeds
-    if (live) P.lam[gidx] = lam_r;
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+      if (live[s]) P.lam[gidx[s]] = lam[s];
     for (int q = r; q < Q; q += G) {
       double u[M];
 #pragma unroll

@@ -159,6 +159,22 @@ size_t dual_lds_bytes(int M, int NP, int Q, int kp, int waves) {
   return f(std::integral_constant<int, 4>{});
 }
 
+// cells one wavefront of the Newton kernel works on
+int dual_cells_per_wave(int M, int NP) {
+  auto f = [&](auto tag) -> int {
+    constexpr int MM = decltype(tag)::value;
+    switch (NP) {
+      case 8: return NC<MM, 8>::CPW;
+      case 16: return NC<MM, 16>::CPW;
+      case 32: return NC<MM, 32>::CPW;
+      default: return NC<MM, 64>::CPW;
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  if (M == 3) return f(std::integral_constant<int, 3>{});
+  return f(std::integral_constant<int, 4>{});
+}
+
 // basis-table columns the Newton kernel's Hessian segments read
 int dual_table_columns(int M, int NP) {
   auto f = [&](auto tag) -> int {
@@ -248,7 +264,7 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
 ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int cells) {
   DualFn fn = pick_dual(P.M, P.NP);
   if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-  const int per_block = P.dual_waves * (64 / P.NP);
+  const int per_block = P.dual_waves * dual_cells_per_wave(P.M, P.NP);
   const int items = d.list_cap > 0 ? kSlots * d.list_cap : cells;
   const int blocks = (items + per_block - 1) / per_block;
   if (blocks == 0) return IPM_OK;
