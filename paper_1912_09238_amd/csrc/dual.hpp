@@ -184,8 +184,9 @@ __device__ __forceinline__ double recip(double x) {
 // lane's share of <s_*> to ssum.  Returns the admissible flag.
 template <int M>
 __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lamS, int Nc,
-                                          const double* phiL, const double* wphiL, int q0,
-                                          int step, double* US, double* JS, double& ssum) {
+                                          const double* phiL, const double* wq, int wstride,
+                                          int q0, int step, double* US, double* JS,
+                                          double& ssum) {
   constexpr int NJ = M * (M + 1) / 2;
   int ok = 1;
 #pragma unroll 1
@@ -206,7 +207,7 @@ __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lam
     for (int a = 0; a < M; ++a) US[q * M + a] = u[a];
 #pragma unroll
     for (int k = 0; k < NJ; ++k) JS[q * NJ + k] = J[k];
-    ssum = fma(wphiL[q * P.kp], ss, ssum);
+    ssum = fma(wq[q * wstride], ss, ssum);
   }
   return ok;
 }
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
     double ssum = 0.0;
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
     auto group_all = [&](int v) -> int { return (__ballot(!v) & gmask) == 0ull ? 1 : 0; };
-    int ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, r, G, US, JS, ssum));
+    int ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, r, G, US, JS, ssum));
     wave_sync();
 
     double g[R];
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
         }
         wave_sync();
         ssum = 0.0;
-        ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, r, G, US, JS, ssum));
+        ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, r, G, US, JS, ssum));
         wave_sync();
         if (!ls) {
           accepted = 1;

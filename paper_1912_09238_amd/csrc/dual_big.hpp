@@ -1,0 +1,326 @@
+// Dual Newton solve for cells with more than 64 unknowns (n = m N up to 16 T):
+// one 256-thread workgroup per cell.
+//
+// The steps are those of the small-cell kernel (ansatz eq:ansatz, gradient of
+// eq:L and the test eq:tauCrit, Hessian eq:dualIterationFunction, step
+// eq:dualIteration1 with the backtracking rule of the line search); only the
+// layout differs:
+//   - threads over quadrature nodes for the ansatz, over unknowns for the
+//     gradient (unknown r = i M + a, as everywhere in this library);
+//   - the Hessian as a 16 x 16 grid of T x T register tiles: thread (tr, tc)
+//     holds rows tr + 16 i and columns tc + 16 j.  Since M divides 16, all
+//     rows of a tile share the variable a = tr mod M and all columns the
+//     variable b = tc mod M, so a tile's entries take one entry J_ab of the
+//     closure Jacobian per node and the sum over nodes is a rank-1 update;
+//   - Gauss-Jordan without pivoting (H is SPD): the owners of the pivot
+//     column publish it to LDS, one barrier per step; every thread reads the
+//     column entries of its rows (multipliers) and, by symmetry of the
+//     trailing Schur complement, of its columns (the pivot row).  Only
+//     columns right of the pivot are updated: the eliminated pivot rows above
+//     are no longer symmetric with their columns.
+#pragma once
+
+#include "dual.hpp"
+
+namespace ipm {
+
+template <int M, int T>
+struct BigCfg {
+  static_assert(16 % M == 0, "tile variables need M | 16");
+  static constexpr int NPB = 16 * T;  // unknowns incl. identity padding
+  static constexpr int NJ = M * (M + 1) / 2;
+  __host__ __device__ static size_t lds_bytes(int Q, int kp) {
+    // phi [Q][kp]; w [Q]; lam [NPB]; U [Q][M]; J [Q][NJ]; column [2][NPB];
+    // pivot-row rhs [2]; reduction scratch [4][8]
+    return sizeof(double) * (static_cast<size_t>(Q) * kp + Q + NPB +
+                             static_cast<size_t>(Q) * (M + NJ) + 2 * NPB + 2 + 32);
+  }
+};
+
+// Sum over the workgroup (256 threads, all active) of K values per thread.
+// Fixed reduction order: identical results in every thread and every run.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w * 8 + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (red[k] + red[8 + k]) + (red[16 + k] + red[24 + k]);
+  __syncthreads();
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
+  using Cfg = BigCfg<M, T>;
+  constexpr int NPB = Cfg::NPB, NJ = Cfg::NJ;
+  if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
+  if (P.mode == 0 && blockIdx.x == 0) {
+    StepCtrl* C = P.ctrl;
+    for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
+      C->amax[P.parity ^ 1][0][k * kSlotStride] = 0ull;
+      C->amax[P.parity ^ 1][1][k * kSlotStride] = 0ull;
+      C->list_len[(P.parity ^ 1) * kSlots * kSlotStride + k * kSlotStride] = 0u;
+    }
+  }
+  // the cell of this workgroup: entry-major over the 64 lists, or in order
+  const int item = blockIdx.x;
+  int cell = -1;
+  if (P.list_cap > 0) {
+    const int slot = item & (kSlots - 1), entry = item >> 6;
+    const int len =
+        static_cast<int>(P.ctrl->list_len[P.parity * kSlots * kSlotStride + slot * kSlotStride]);
+    if (entry < min(len, P.list_cap)) cell = P.lists[static_cast<size_t>(slot) * P.list_cap + entry];
+  } else if (item < P.cells) {
+    cell = item;
+  }
+  if (cell < 0) return;  // uniform over the workgroup
+
+  const int Q = P.Q, kp = P.kp, N = P.N;
+  const int tid = threadIdx.x;
+  extern __shared__ double smem[];
+  double* phiL = smem;
+  double* wL = phiL + Q * kp;      // [Q] weights (w phi_0, phi_0 = 1)
+  double* lamS = wL + Q;           // [NPB]
+  double* US = lamS + NPB;         // [Q][M]
+  double* JS = US + Q * M;         // [Q][NJ]
+  double* col = JS + Q * NJ;       // [2][NPB]
+  double* xk = col + 2 * NPB;      // [2]
+  double* red = xk + 2;            // [32]
+  for (int k = tid; k < Q * kp; k += 256) phiL[k] = P.phi[k];
+  for (int q = tid; q < Q; q += 256) wL[q] = P.wphi[static_cast<size_t>(q) * kp];
+
+  const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
+  const int nc = Nc * M;
+  // unknown owned by this thread (gradient, right-hand side, step)
+  const bool row_live = tid < nc;
+  const int ri = tid / M, ra = tid % M;
+  const size_t gidx = static_cast<size_t>(cell) * M * N + static_cast<size_t>(ra) * N + ri;
+  double lam = row_live ? P.lam[gidx] : 0.0;
+  const double uh = row_live ? P.uhat[gidx] : 0.0;
+  if (tid < NPB) lamS[tid] = row_live ? lam : 0.0;
+  __syncthreads();
+
+  // tile coordinates
+  const int tr = tid >> 4, tc = tid & 15;
+  const int jidx = Packed<M>::idx(tr % M, tc % M);
+
+  int its = 0;
+  unsigned status = 0;
+  double ssum = 0.0;
+  int ok = eval_nodes<M>(P, lamS, Nc, phiL, wL, 1, tid, 256, US, JS, ssum);
+  ok = __syncthreads_and(ok);
+
+  double g = 0.0;
+  auto gradient = [&]() -> double {
+    double gg = 0.0;
+    if (row_live) {
+      for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra] * wL[q], phiL[q * kp + ri], gg);
+      gg -= uh;
+    }
+    g = gg;
+    double e2[M];
+#pragma unroll
+    for (int b = 0; b < M; ++b) e2[b] = (row_live && ra == b) ? gg * gg : 0.0;
+    block_sum<M>(e2, red);
+    double res = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) res += sqrt(e2[b]);
+    return res;
+  };
+
+  double res = 0.0;
+  if (ok) res = gradient();
+  else status |= kStRealizability;
+
+  while (ok) {
+    if (!(res == res) || res > 1e300) {
+      status |= kStNonfinite;
+      break;
+    }
+    if (!P.one_shot) {
+      if (res < P.tau) break;
+      if (its >= P.max_newton) {
+        status |= kStNewton;
+        break;
+      }
+    }
+    // ---- Hessian tiles
+    double H[T][T];
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int j = 0; j < T; ++j) H[i][j] = 0.0;
+    {
+      int li[T], lj[T];
+      double mi[T], mj[T];
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const int r = tr + 16 * i;
+        li[i] = r < nc ? r / M : 0;
+        mi[i] = r < nc ? 1.0 : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const int c = tc + 16 * j;
+        lj[j] = c < nc ? c / M : 0;
+        mj[j] = c < nc ? 1.0 : 0.0;
+      }
+      for (int q = 0; q < Q; ++q) {
+        const double s = JS[q * NJ + jidx] * wL[q];
+        double lv[T], rv[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) lv[i] = phiL[q * kp + li[i]] * (s * mi[i]);
+#pragma unroll
+        for (int j = 0; j < T; ++j) rv[j] = phiL[q * kp + lj[j]] * mj[j];
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int j = 0; j < T; ++j) H[i][j] = fma(lv[i], rv[j], H[i][j]);
+      }
+      // identity beyond the cell's unknowns
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int r = tr + 16 * i, c = tc + 16 * j;
+          if (r >= nc || c >= nc) H[i][j] = (r == c) ? 1.0 : 0.0;
+        }
+    }
+    // ---- Gauss-Jordan solve H d = g
+    double x = g, dg = 1.0;
+    int pd_ok = 1;
+#pragma unroll
+    for (int jb = 0; jb < T; ++jb) {
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = jb * 16 + kk;
+        if (k >= nc) break;  // uniform
+        double* cb = col + (k & 1) * NPB;
+        if (tc == kk) {
+#pragma unroll
+          for (int i = 0; i < T; ++i) cb[tr + 16 * i] = H[i][jb];
+        }
+        if (tid == k) xk[k & 1] = x;
+        __syncthreads();
+        const double piv = cb[k];
+        const double gk = xk[k & 1];
+        pd_ok &= piv > 0.0 ? 1 : 0;
+        const double rp = recip(piv);
+        double f[T], pr[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+          const int r = tr + 16 * i;
+          f[i] = (r == k) ? 0.0 : cb[r] * rp;
+        }
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int c = tc + 16 * j;
+          pr[j] = (c > k) ? cb[c] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int j = 0; j < T; ++j) H[i][j] = fma(-f[i], pr[j], H[i][j]);
+        if (tid < NPB) {
+          if (tid == k) dg = piv;
+          else x = fma(-(cb[tid] * rp), gk, x);
+        }
+      }
+    }
+    if (!pd_ok) {  // uniform: every thread read the same pivots
+      status |= kStCholesky;
+      break;
+    }
+    const double d = row_live ? x * recip(dg) : 0.0;
+    // ---- step length
+    const bool ls = !P.one_shot && res > 1e-6;
+    double L0 = 0.0, slope = 0.0;
+    if (ls) {
+      double v2[2] = {ssum - (row_live ? lam * uh : 0.0), row_live ? g * d : 0.0};
+      block_sum<2>(v2, red);
+      L0 = v2[0];
+      slope = v2[1];
+    }
+    double t = 1.0, lt = lam;
+    int accepted = 0;
+#pragma unroll 1
+    for (int h = 0; h <= 60; ++h) {
+      lt = lam - t * d;
+      if (tid < NPB) lamS[tid] = row_live ? lt : 0.0;
+      __syncthreads();
+      ssum = 0.0;
+      ok = eval_nodes<M>(P, lamS, Nc, phiL, wL, 1, tid, 256, US, JS, ssum);
+      ok = __syncthreads_and(ok);
+      if (!ls) {
+        accepted = 1;
+        break;
+      }
+      if (ok) {
+        double v1[1] = {ssum - (row_live ? lt * uh : 0.0)};
+        block_sum<1>(v1, red);
+        if (v1[0] <= L0 - 1e-4 * t * slope) {
+          accepted = 1;
+          break;
+        }
+      }
+      t *= 0.5;
+    }
+    if (!accepted) {
+      status |= kStLineSearch;
+      break;
+    }
+    lam = lt;
+    ++its;
+    if (!ok) {
+      status |= kStRealizability;
+      break;
+    }
+    res = gradient();
+    if (P.one_shot) break;
+  }
+
+  // ---- write back: dual, nodal ansatz, wave speeds
+  if (row_live) P.lam[gidx] = lam;
+  double sx = 0.0, sy = 0.0;
+  for (int q = tid; q < Q; q += 256) {
+    double u[M];
+#pragma unroll
+    for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+#pragma unroll
+    for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
+    double ax, ay;
+    wave_speeds<M>(P.cp.gamma, P.dim, u, ax, ay);
+    sx = nan_max(sx, ax);
+    sy = nan_max(sy, ay);
+  }
+  sx = wave_max(sx);
+  sy = wave_max(sy);
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = sx;
+    red[2 * (tid >> 6) + 1] = sy;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double mx = nan_max(nan_max(red[0], red[2]), nan_max(red[4], red[6]));
+    const double my = nan_max(nan_max(red[1], red[3]), nan_max(red[5], red[7]));
+    const int slot = (blockIdx.x & (kSlots - 1)) * kSlotStride;
+    if (P.mode == 0) {
+      unsigned long long* bs = P.blk_stats + 2 * blockIdx.x;
+      bs[0] += static_cast<unsigned long long>(its);
+      if (static_cast<unsigned long long>(its) > bs[1]) bs[1] = static_cast<unsigned long long>(its);
+      if (status) atomicOr(&P.ctrl->status, status);
+      atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
+      if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));
+    } else {
+      if (status) atomicOr(&P.ctrl->setup_status, status);
+      atomicMax(&P.ctrl->amax[0][0][slot], speed_bits(mx));
+      if (P.dim == 2) atomicMax(&P.ctrl->amax[0][1][slot], speed_bits(my));
+    }
+  }
+}
+
+}  // namespace ipm

@@ -16,6 +16,7 @@
 
 #include "ipm.h"
 #include "dual.hpp"
+#include "dual_big.hpp"
 #include "setup.hpp"
 #include "tables.hpp"
 #include "update.hpp"
@@ -28,6 +29,7 @@ thread_local std::string g_create_error;
 
 struct Problem {
   int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, NP = 8, UG = 16;
+  int T = 0;  // > 0: cells of more than 64 unknowns, workgroup kernel with T x T tiles
   int nx = 1, ny = 1, cells = 1;
   int flux = 0, max_newton = 100, one_shot = 0, precision = 0;
   int bc[4] = {0, 0, 0, 0};
@@ -109,6 +111,37 @@ DualFn dual_fn(int NP) {
   return nullptr;
 }
 
+
+template <int M>
+DualFn big_fn(int T) {
+  switch (T) {
+    case 5: return newton_big_kernel<M, 5>;
+    case 6: return newton_big_kernel<M, 6>;
+    case 8: return newton_big_kernel<M, 8>;
+    case 9: return newton_big_kernel<M, 9>;
+  }
+  return nullptr;
+}
+
+DualFn pick_big(int M, int T) {
+  if (M == 1) return big_fn<1>(T);
+  if (M == 4) return big_fn<4>(T);
+  return nullptr;
+}
+
+size_t big_lds_bytes(int M, int T, int Q, int kp) {
+  auto f = [&](auto tag) -> size_t {
+    constexpr int MM = decltype(tag)::value;
+    switch (T) {
+      case 5: return BigCfg<MM, 5>::lds_bytes(Q, kp);
+      case 6: return BigCfg<MM, 6>::lds_bytes(Q, kp);
+      case 8: return BigCfg<MM, 8>::lds_bytes(Q, kp);
+      default: return BigCfg<MM, 9>::lds_bytes(Q, kp);
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  return f(std::integral_constant<int, 4>{});
+}
 
 DualFn pick_dual(int M, int NP) {
   if (M == 1) return dual_fn<1>(NP);
@@ -207,16 +240,29 @@ void free_problem(Problem* P) {
 // Launch geometry of a problem's kernels.
 ipm_status plan(ipm_ctx* ctx, Problem& P) {
   const int n = P.M * P.N;
-  if (n > 64)
-    return fail(ctx, IPM_E_ARG,
-                "m*N = " + std::to_string(n) + " unknowns per cell exceeds 64 (supported range of the "
-                "fused dual kernel)");
-  P.NP = pow2_at_least(n, 8);
-  P.kp = std::max(P.N, dual_table_columns(P.M, P.NP));
-  P.dual_waves = 4;
-  while (P.dual_waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves) > 64 * 1024)
-    P.dual_waves >>= 1;
-  P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves);
+  if (n > 64) {
+    // workgroup per cell; the tile layout needs m | 16 (m = 1 or 4)
+    if (16 % P.M != 0)
+      return fail(ctx, IPM_E_ARG,
+                  "m*N = " + std::to_string(n) + " > 64 unknowns per cell is supported for m = 1 and "
+                  "m = 4 only");
+    if (n > 144)
+      return fail(ctx, IPM_E_ARG,
+                  "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
+    P.T = n <= 80 ? 5 : n <= 96 ? 6 : n <= 128 ? 8 : 9;
+    P.NP = 16 * P.T;
+    P.kp = P.N;
+    P.dual_waves = 4;
+    P.dual_lds = big_lds_bytes(P.M, P.T, P.Q, P.kp);
+  } else {
+    P.T = 0;
+    P.NP = pow2_at_least(n, 8);
+    P.kp = std::max(P.N, dual_table_columns(P.M, P.NP));
+    P.dual_waves = 4;
+    while (P.dual_waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves) > 64 * 1024)
+      P.dual_waves >>= 1;
+    P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves);
+  }
   if (P.dual_lds > ctx->max_lds)
     return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
                                     std::to_string(P.Q) + ")");
@@ -262,6 +308,15 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
 // Newton kernel over all cells in order (setup, one-shot) or over the
 // screened lists (d.list_cap > 0)
 ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int cells) {
+  if (P.T > 0) {
+    DualFn fn = pick_big(P.M, P.T);
+    if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
+    const int blocks = d.list_cap > 0 ? kSlots * d.list_cap : cells;
+    if (blocks == 0) return IPM_OK;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), P.dual_lds, ctx->stream, d);
+    HIPCHK(ctx, hipGetLastError());
+    return IPM_OK;
+  }
   DualFn fn = pick_dual(P.M, P.NP);
   if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
   const int per_block = P.dual_waves * dual_cells_per_wave(P.M, P.NP);
@@ -364,6 +419,10 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   for (int M : {1, 3, 4})
     for (int G : {16, 32, 64})
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  for (int M : {1, 4})
+    for (int T : {5, 6, 8, 9})
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
 
   (void)hipGetLastError();  // the request is best effort; do not leave a sticky error

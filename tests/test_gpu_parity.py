@@ -182,3 +182,42 @@ def test_newton_failure_is_sticky(gpu_ctx, orc):
     with pytest.raises(binding.IpmError):
         # the initial dual cannot converge in one iteration to 1e-14
         gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+
+
+# ---- cells of more than 64 unknowns: workgroup-per-cell Newton kernel
+
+def test_euler2d_degree5_large_cells(gpu_ctx, orc):
+    # N = 21, n = 84 unknowns per cell, 8 x 8 nodes: the 2D throughput workload's cell size
+    spec = W.bump2d(n=16, degree=5, qpd=8, t_end=0.0)
+    spec["ny"] = 12
+    info, got, _, oinfo, o = _run_both(gpu_ctx, orc, spec, 8)
+    _check(info, got, oinfo, o)
+
+
+def test_euler2d_three_uncertainties_degree4_uneven(gpu_ctx, orc):
+    # N = 35, n = 140 at degree 4, 5^3 nodes; per-cell degrees 0..4 (n = 4 .. 140)
+    spec = W.bump2d(n=10, degree=4, qpd=5, p=3, t_end=0.0, v1_spread=0.2)
+    spec["ny"] = 7
+    rng = np.random.default_rng(1912)
+    cd = rng.integers(0, 5, size=spec["nx"] * spec["ny"]).astype(np.int8)
+    info, got, _, oinfo, o = _run_both(gpu_ctx, orc, spec, 5, cell_degree=cd)
+    _check(info, got, oinfo, o)
+
+
+def test_burgers_two_uncertainties_degree11(gpu_ctx, orc):
+    # m = 1, N = 78 unknowns, 12 x 12 nodes, log-barrier entropy
+    spec = W.burgers_shock(nx=40, degree=11, qpd=12, t_end=0.03)
+    spec["p"] = 2
+    info, got, _, oinfo, o = _run_both(gpu_ctx, orc, spec, 200)
+    assert info["done"] == 1
+    _check(info, got, oinfo, o)
+
+
+def test_large_cells_with_three_variables_are_rejected(gpu_ctx):
+    from paper_1912_09238_amd import binding
+    spec = W.sod(nx=8, degree=4, qpd=5)
+    spec["p"] = 3  # N = 35, n = 105 > 64 with m = 3
+    nodes, _ = binding.quadrature(3, 5)
+    with pytest.raises(binding.IpmError) as e:
+        gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+    assert e.value.code == -1
