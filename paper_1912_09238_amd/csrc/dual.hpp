@@ -38,6 +38,12 @@ namespace ipm {
 
 constexpr int kSlots = 64;
 constexpr int kSlotStride = 16;  // 128-byte spacing of atomic slots
+// Newton size classes of a cell with n unknowns: groups of 8, 16, 32, 64
+// lanes (n <= 64) or the workgroup-per-cell kernel (n > 64)
+constexpr int kCls = 5;
+__host__ __device__ inline int size_class(int n) {
+  return n > 64 ? 4 : n > 32 ? 3 : n > 16 ? 2 : n > 8 ? 1 : 0;
+}
 
 struct StepCtrl {
   double t[2];                      // time by step parity
@@ -52,10 +58,15 @@ struct StepCtrl {
   unsigned int pad_;
   // [parity][direction][slot * kSlotStride] speed bit patterns
   unsigned long long amax[2][2][kSlots * kSlotStride];
-  // [parity][slot * kSlotStride] lengths of the 64 lists of cells that
-  // need Newton steps
-  unsigned int list_len[2 * kSlots * kSlotStride];
+  // [parity][class][slot * kSlotStride] lengths of the 64 lists per size
+  // class of cells that need Newton steps
+  unsigned int list_len[2 * kCls * kSlots * kSlotStride];
 };
+
+__host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) {
+  return (static_cast<size_t>(parity) * kCls + cls) * kSlots * kSlotStride +
+         static_cast<size_t>(slot) * kSlotStride;
+}
 
 struct DualParams {
   const double* __restrict__ phi;   // [Q][kp] Phi, zero padded to kp columns
@@ -73,8 +84,12 @@ struct DualParams {
   int dim;
   StepCtrl* ctrl;
   int parity;
-  int* __restrict__ lists;          // [64][list_cap] cells needing Newton steps (this step)
-  int list_cap;                     // 0: newton_kernel takes cells in order
+  int* __restrict__ lists;          // [64][list_cap] cells of this class needing Newton steps
+  int list_cap;                     // 0: cells from `order` (or 0..cells-1 if null)
+  int cls;                          // size class of the launch
+  int reset_next;                   // block 0 clears the next step's lists and speed slots
+  const int* __restrict__ order;    // [order_len] cells of this class, ascending
+  int order_len;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -249,37 +264,43 @@ struct NewtonCfg {
 // the same for every lane, so they need not occupy LDS bandwidth.
 typedef const __attribute__((address_space(4))) double* const_dptr;
 
+// The cell of work item `item`: entry-major over the 64 lists of the launch's
+// size class, or the class's cells in ascending order.
+__device__ __forceinline__ int work_cell(const DualParams& P, int item) {
+  if (P.list_cap > 0) {
+    const int slot = item & (kSlots - 1), entry = item >> 6;
+    const int len = static_cast<int>(P.ctrl->list_len[list_len_index(P.parity, P.cls, slot)]);
+    return entry < min(len, P.list_cap) ? P.lists[static_cast<size_t>(slot) * P.list_cap + entry]
+                                        : -1;
+  }
+  if (P.order) return item < P.order_len ? P.order[item] : -1;
+  return item < P.cells ? item : -1;
+}
+
+__device__ __forceinline__ void reset_next_step(const DualParams& P) {
+  StepCtrl* C = P.ctrl;
+  for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
+    C->amax[P.parity ^ 1][0][k * kSlotStride] = 0ull;
+    C->amax[P.parity ^ 1][1][k * kSlotStride] = 0ull;
+  }
+  for (int k = threadIdx.x; k < kCls * kSlots; k += blockDim.x)
+    C->list_len[list_len_index(P.parity ^ 1, k / kSlots, k % kSlots)] = 0u;
+}
+
 template <int M, int NP>
-__global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
+__device__ __forceinline__ void newton_body(const DualParams& P, const int blk) {
   using Cfg = NewtonCfg<M, NP>;
   constexpr int G = Cfg::G, CPW = Cfg::CPW, NJ = Cfg::NJ, R = Cfg::R;
   constexpr bool kDpp = Cfg::kDpp;
   if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
-  if (P.mode == 0 && blockIdx.x == 0) {
-    // the flux update of this step fills the next step's speed slots and list
-    StepCtrl* C = P.ctrl;
-    for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
-      C->amax[P.parity ^ 1][0][k * kSlotStride] = 0ull;
-      C->amax[P.parity ^ 1][1][k * kSlotStride] = 0ull;
-      C->list_len[(P.parity ^ 1) * kSlots * kSlotStride + k * kSlotStride] = 0u;
-    }
-  }
+  // the flux update of this step fills the next step's speed slots and lists
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   const int waves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int grp = lane / G;
   const int r = lane % G;
-  // work item of this group: entry-major over the 64 lists, or the cell index
-  const int item = (blockIdx.x * waves + wave) * CPW + grp;
-  int cell = -1;
-  if (P.list_cap > 0) {
-    const int slot = item & (kSlots - 1), entry = item >> 6;
-    const int len =
-        static_cast<int>(P.ctrl->list_len[P.parity * kSlots * kSlotStride + slot * kSlotStride]);
-    if (entry < min(len, P.list_cap)) cell = P.lists[static_cast<size_t>(slot) * P.list_cap + entry];
-  } else if (item < P.cells) {
-    cell = item;
-  }
+  const int cell = work_cell(P, (blk * waves + wave) * CPW + grp);
   if (!__syncthreads_or(cell >= 0)) return;
 
   const int Q = P.Q, kp = P.kp, N = P.N;
@@ -618,9 +639,9 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
       mx = nan_max(mx, stats[2 * waves * CPW + 2 * w]);
       my = nan_max(my, stats[2 * waves * CPW + 2 * w + 1]);
     }
-    const int slot = (blockIdx.x & (kSlots - 1)) * kSlotStride;
+    const int slot = (blk & (kSlots - 1)) * kSlotStride;
     if (P.mode == 0) {
-      unsigned long long* bs = P.blk_stats + 2 * blockIdx.x;
+      unsigned long long* bs = P.blk_stats + 2 * blk;
       bs[0] += sum_its;
       if (max_its > bs[1]) bs[1] = max_its;
       if (st) atomicOr(&P.ctrl->status, st);
@@ -633,6 +654,29 @@ __global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
       if (P.dim == 2) atomicMax(&P.ctrl->amax[0][1][slot], speed_bits(my));
     }
   }
+}
+
+template <int M, int NP>
+__global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
+  newton_body<M, NP>(P, blockIdx.x);
+}
+
+// Problem k of a batched launch owns blocks begin[k] .. begin[k+1]-1.
+__device__ __forceinline__ int batch_problem(const int* __restrict__ begin, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int M, int NP>
+__global__ __launch_bounds__(256) void newton_batched(const DualParams* __restrict__ PP,
+                                                      const int* __restrict__ begin, int n) {
+  const int k = batch_problem(begin, n, blockIdx.x);
+  newton_body<M, NP>(PP[k], blockIdx.x - begin[k]);
 }
 
 }  // namespace ipm

@@ -55,29 +55,12 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
 }
 
 template <int M, int T>
-__global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
+__device__ __forceinline__ void newton_big_body(const DualParams& P, const int blk) {
   using Cfg = BigCfg<M, T>;
   constexpr int NPB = Cfg::NPB, NJ = Cfg::NJ;
   if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
-  if (P.mode == 0 && blockIdx.x == 0) {
-    StepCtrl* C = P.ctrl;
-    for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
-      C->amax[P.parity ^ 1][0][k * kSlotStride] = 0ull;
-      C->amax[P.parity ^ 1][1][k * kSlotStride] = 0ull;
-      C->list_len[(P.parity ^ 1) * kSlots * kSlotStride + k * kSlotStride] = 0u;
-    }
-  }
-  // the cell of this workgroup: entry-major over the 64 lists, or in order
-  const int item = blockIdx.x;
-  int cell = -1;
-  if (P.list_cap > 0) {
-    const int slot = item & (kSlots - 1), entry = item >> 6;
-    const int len =
-        static_cast<int>(P.ctrl->list_len[P.parity * kSlots * kSlotStride + slot * kSlotStride]);
-    if (entry < min(len, P.list_cap)) cell = P.lists[static_cast<size_t>(slot) * P.list_cap + entry];
-  } else if (item < P.cells) {
-    cell = item;
-  }
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  const int cell = work_cell(P, blk);
   if (cell < 0) return;  // uniform over the workgroup
 
   const int Q = P.Q, kp = P.kp, N = P.N;
@@ -307,9 +290,9 @@ __global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
   if (tid == 0) {
     const double mx = nan_max(nan_max(red[0], red[2]), nan_max(red[4], red[6]));
     const double my = nan_max(nan_max(red[1], red[3]), nan_max(red[5], red[7]));
-    const int slot = (blockIdx.x & (kSlots - 1)) * kSlotStride;
+    const int slot = (blk & (kSlots - 1)) * kSlotStride;
     if (P.mode == 0) {
-      unsigned long long* bs = P.blk_stats + 2 * blockIdx.x;
+      unsigned long long* bs = P.blk_stats + 2 * blk;
       bs[0] += static_cast<unsigned long long>(its);
       if (static_cast<unsigned long long>(its) > bs[1]) bs[1] = static_cast<unsigned long long>(its);
       if (status) atomicOr(&P.ctrl->status, status);
@@ -321,6 +304,18 @@ __global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
       if (P.dim == 2) atomicMax(&P.ctrl->amax[0][1][slot], speed_bits(my));
     }
   }
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
+  newton_big_body<M, T>(P, blockIdx.x);
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void newton_big_batched(const DualParams* __restrict__ PP,
+                                                          const int* __restrict__ begin, int n) {
+  const int k = batch_problem(begin, n, blockIdx.x);
+  newton_big_body<M, T>(PP[k], blockIdx.x - begin[k]);
 }
 
 }  // namespace ipm

@@ -27,9 +27,24 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Newton launch configuration of one size class of a problem's cells
+struct DualClass {
+  bool configured = false;  // kernel chosen (cells of the class, or the ghosts' full size)
+  int NP = 8;               // lanes per cell (small kernel) or 16 T (workgroup kernel)
+  int T = 0;                // > 0: workgroup kernel with T x T tiles
+  int waves = 4;            // small kernel: wavefronts per block
+  size_t lds = 0;
+  int count = 0;            // cells of the class
+  int cap = 0;              // list capacity per slot
+  int* d_lists = nullptr;   // [2][64][cap] Newton lists by step parity
+  int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
+  int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
+};
+
 struct Problem {
-  int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, NP = 8, UG = 16;
-  int T = 0;  // > 0: cells of more than 64 unknowns, workgroup kernel with T x T tiles
+  int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, UG = 16;
+  int full_cls = 0;  // class of a cell with all N modes (ghosts)
+  DualClass cls[kCls];
   int nx = 1, ny = 1, cells = 1;
   int flux = 0, max_newton = 100, one_shot = 0, precision = 0;
   int bc[4] = {0, 0, 0, 0};
@@ -45,14 +60,12 @@ struct Problem {
   double* d_ghost = nullptr;
   double* d_res = nullptr;
   unsigned long long* d_blk = nullptr;
-  int* d_lists = nullptr;       // [2][64][list_cap] Newton lists by step parity
-  int list_cap = 0;
   int8_t* d_cellN = nullptr;
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;
-  int upd_blocks = 1, dual_blocks = 1, dual_waves = 4;
-  size_t dual_lds = 0, upd_lds = 0;
+  int upd_blocks = 1, dual_blocks = 1;
+  size_t upd_lds = 0;
 };
 
 }  // namespace
@@ -115,6 +128,9 @@ DualFn dual_fn(int NP) {
 template <int M>
 DualFn big_fn(int T) {
   switch (T) {
+    case 1: return newton_big_kernel<M, 1>;
+    case 2: return newton_big_kernel<M, 2>;
+    case 4: return newton_big_kernel<M, 4>;
     case 5: return newton_big_kernel<M, 5>;
     case 6: return newton_big_kernel<M, 6>;
     case 8: return newton_big_kernel<M, 8>;
@@ -133,6 +149,9 @@ size_t big_lds_bytes(int M, int T, int Q, int kp) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
     switch (T) {
+      case 1: return BigCfg<MM, 1>::lds_bytes(Q, kp);
+      case 2: return BigCfg<MM, 2>::lds_bytes(Q, kp);
+      case 4: return BigCfg<MM, 4>::lds_bytes(Q, kp);
       case 5: return BigCfg<MM, 5>::lds_bytes(Q, kp);
       case 6: return BigCfg<MM, 6>::lds_bytes(Q, kp);
       case 8: return BigCfg<MM, 8>::lds_bytes(Q, kp);
@@ -231,51 +250,81 @@ Problem* get(ipm_ctx* ctx, int id) {
 
 void free_problem(Problem* P) {
   if (!P) return;
-  void* ptrs[] = {P->d_phi,   P->d_wphi,  P->d_u[0], P->d_u[1],  P->d_lam,   P->d_nodal,
-                  P->d_ghost, P->d_res,   P->d_blk,  P->d_lists, P->d_cellN, P->d_ctrl};
+  void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN, P->d_ctrl};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (DualClass& c : P->cls) {
+    if (c.d_lists) (void)hipFree(c.d_lists);
+    if (c.d_order) (void)hipFree(c.d_order);
+  }
 }
 
-// Launch geometry of a problem's kernels.
-ipm_status plan(ipm_ctx* ctx, Problem& P) {
+// Launch geometry of a problem's kernels.  counts[c]: cells per size class.
+ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   const int n = P.M * P.N;
-  if (n > 64) {
-    // workgroup per cell; the tile layout needs m | 16 (m = 1 or 4)
-    if (16 % P.M != 0)
-      return fail(ctx, IPM_E_ARG,
-                  "m*N = " + std::to_string(n) + " > 64 unknowns per cell is supported for m = 1 and "
-                  "m = 4 only");
-    if (n > 144)
-      return fail(ctx, IPM_E_ARG,
-                  "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
-    P.T = n <= 80 ? 5 : n <= 96 ? 6 : n <= 128 ? 8 : 9;
-    P.NP = 16 * P.T;
-    P.kp = P.N;
-    P.dual_waves = 4;
-    P.dual_lds = big_lds_bytes(P.M, P.T, P.Q, P.kp);
-  } else {
-    P.T = 0;
-    P.NP = pow2_at_least(n, 8);
-    P.kp = std::max(P.N, dual_table_columns(P.M, P.NP));
-    P.dual_waves = 4;
-    while (P.dual_waves > 1 && dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves) > 64 * 1024)
-      P.dual_waves >>= 1;
-    P.dual_lds = dual_lds_bytes(P.M, P.NP, P.Q, P.kp, P.dual_waves);
+  P.full_cls = size_class(n);
+  for (int c = 0; c < kCls; ++c) {
+    P.cls[c] = DualClass{};
+    P.cls[c].count = counts[c];
+    P.cls[c].configured = counts[c] > 0 || c == P.full_cls;
   }
-  if (P.dual_lds > ctx->max_lds)
-    return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
-                                    std::to_string(P.Q) + ")");
+  P.kp = P.N;
+  for (int c = 0; c < kCls; ++c) {
+    DualClass& D = P.cls[c];
+    if (!D.configured) continue;
+    if (c == 4) {
+      // workgroup per cell; the tile layout needs m | 16 (m = 1 or 4)
+      if (16 % P.M != 0)
+        return fail(ctx, IPM_E_ARG,
+                    "m*N = " + std::to_string(n) + " > 64 unknowns per cell is supported for m = 1 "
+                    "and m = 4 only");
+      if (n > 144)
+        return fail(ctx, IPM_E_ARG, "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
+      D.T = n <= 80 ? 5 : n <= 96 ? 6 : n <= 128 ? 8 : 9;
+      D.NP = 16 * D.T;
+    } else {
+      D.NP = 8 << c;
+      P.kp = std::max(P.kp, dual_table_columns(P.M, D.NP));
+    }
+  }
   P.UG = pow2_at_least(std::min(64, std::max(P.Q, n)), 16);
   const int ucpb = 4 * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
   P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
                                 2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256);
-  // list l receives the routed cells of update blocks b = l (mod 64)
-  P.list_cap = ((P.upd_blocks + kSlots - 1) / kSlots) * ucpb;
-  // one Newton block per list entry (time steps) or per cell (setup, one-shot)
-  P.dual_blocks = std::max(kSlots * P.list_cap, P.cells);
   if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
+  P.dual_blocks = 0;
+  for (int c = 0; c < kCls; ++c) {
+    DualClass& D = P.cls[c];
+    if (!D.configured) continue;
+    if (D.T == 0) {
+      D.waves = 4;
+      while (D.waves > 1 && dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves) > 64 * 1024) D.waves >>= 1;
+      D.lds = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves);
+      // many nodes: the per-cell node buffers of a wavefront's cells do not
+      // fit, so the class runs on the workgroup-per-cell kernel
+      if (D.lds > ctx->max_lds && 16 % P.M == 0) {
+        D.T = std::max(1, D.NP / 16);
+        D.NP = 16 * D.T;
+      }
+    }
+    if (D.T > 0) {
+      D.waves = 4;
+      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp);
+    }
+    if (D.lds > ctx->max_lds)
+      return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
+                                      std::to_string(P.Q) + ")");
+    // list l receives the routed cells of update blocks b = l (mod 64)
+    D.cap = D.count > 0 ? std::min(((P.upd_blocks + kSlots - 1) / kSlots) * ucpb, D.count) : 0;
+    const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
+    const int items = std::max(kSlots * D.cap, D.count);
+    D.blk_off = P.dual_blocks;
+    D.blk_cnt = (items + per_block - 1) / per_block;
+    P.dual_blocks += D.blk_cnt;
+  }
+  P.dual_blocks = std::max(P.dual_blocks, 1);
   return IPM_OK;
 }
 
@@ -305,26 +354,58 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   return d;
 }
 
-// Newton kernel over all cells in order (setup, one-shot) or over the
-// screened lists (d.list_cap > 0)
-ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, const DualParams& d, int cells) {
-  if (P.T > 0) {
-    DualFn fn = pick_big(P.M, P.T);
-    if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-    const int blocks = d.list_cap > 0 ? kSlots * d.list_cap : cells;
-    if (blocks == 0) return IPM_OK;
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), P.dual_lds, ctx->stream, d);
-    HIPCHK(ctx, hipGetLastError());
-    return IPM_OK;
+// Newton kernel for size class c: over the class's lists of this step
+// (list_mode) or over its cells in ascending order (setup, one-shot).  The
+// ghosts' setup passes an explicit cell count with all N modes.
+ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool list_mode,
+                       int ghost_cells = -1) {
+  const DualClass& D = P.cls[c];
+  d.cls = c;
+  int items;
+  if (ghost_cells >= 0) {
+    d.list_cap = 0;
+    d.order = nullptr;
+    d.cells = ghost_cells;
+    items = ghost_cells;
+  } else if (list_mode) {
+    d.lists = D.d_lists + static_cast<size_t>(d.parity) * kSlots * D.cap;
+    d.list_cap = D.cap;
+    items = kSlots * D.cap;
+    d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+  } else {
+    d.list_cap = 0;
+    d.order = D.d_order;
+    d.order_len = D.count;
+    items = D.count;
+    d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
   }
-  DualFn fn = pick_dual(P.M, P.NP);
-  if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-  const int per_block = P.dual_waves * dual_cells_per_wave(P.M, P.NP);
-  const int items = d.list_cap > 0 ? kSlots * d.list_cap : cells;
-  const int blocks = (items + per_block - 1) / per_block;
-  if (blocks == 0) return IPM_OK;
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * P.dual_waves), P.dual_lds, ctx->stream, d);
+  if (items == 0) return IPM_OK;
+  if (D.T > 0) {
+    DualFn fn = pick_big(P.M, D.T);
+    if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
+    hipLaunchKernelGGL(fn, dim3(items), dim3(256), D.lds, ctx->stream, d);
+  } else {
+    DualFn fn = pick_dual(P.M, D.NP);
+    if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
+    const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP);
+    const int blocks = (items + per_block - 1) / per_block;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * D.waves), D.lds, ctx->stream, d);
+  }
   HIPCHK(ctx, hipGetLastError());
+  return IPM_OK;
+}
+
+// all Newton launches of one step or of the setup, class by class
+ipm_status launch_dual_classes(ipm_ctx* ctx, const Problem& P, const DualParams& d, bool list_mode) {
+  bool first = true;
+  for (int c = 0; c < kCls; ++c) {
+    if (P.cls[c].count == 0) continue;
+    DualParams dc = d;
+    dc.reset_next = first ? 1 : 0;
+    first = false;
+    ipm_status st = launch_dual(ctx, P, dc, c, list_mode);
+    if (st != IPM_OK) return st;
+  }
   return IPM_OK;
 }
 
@@ -332,10 +413,6 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   const int parity = static_cast<int>(P.step_index & 1);
   DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
                              P.d_cellN, P.d_ctrl, P.d_blk);
-  if (!P.one_shot) {
-    d.lists = P.d_lists + static_cast<size_t>(parity) * kSlots * P.list_cap;
-    d.list_cap = P.list_cap;
-  }
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
   if (ctx->timing) {
     while (ctx->ev.size() < ctx->ev_used + 4) {
@@ -350,7 +427,7 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
     ctx->ev_used += 4;
     HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
   }
-  ipm_status st = launch_dual(ctx, P, d, P.cells);
+  ipm_status st = launch_dual_classes(ctx, P, d, !P.one_shot);
   if (st != IPM_OK) return st;
   if (ctx->timing) {
     HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
@@ -383,8 +460,11 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   u.parity = parity;
   u.tau = P.tau;
   u.one_shot = P.one_shot;
-  u.lists = P.d_lists + static_cast<size_t>(parity ^ 1) * kSlots * P.list_cap;
-  u.list_cap = P.list_cap;
+  for (int c = 0; c < kCls; ++c) {
+    const DualClass& D = P.cls[c];
+    u.lists[c] = D.cap > 0 ? D.d_lists + static_cast<size_t>(parity ^ 1) * kSlots * D.cap : nullptr;
+    u.list_cap[c] = D.cap;
+  }
   UpdFn fn = pick_update(P.M, P.UG);
   hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(256), P.upd_lds, ctx->stream, u);
   HIPCHK(ctx, hipGetLastError());
@@ -421,7 +501,7 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
   for (int M : {1, 4})
-    for (int T : {5, 6, 8, 9})
+    for (int T : {1, 2, 4, 5, 6, 8, 9})
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
 
@@ -523,7 +603,8 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
   const size_t n = static_cast<size_t>(M) * N;
   return sizeof(double) * (3 * cells * n + cells * Q * M + 2 * static_cast<size_t>(Q) * (N + 64) +
                            4 * static_cast<size_t>(Q) * M + cells / 8 + 64) +
-         cells + 2 * cells * sizeof(int) + sizeof(StepCtrl);
+         cells + 2 * (cells + static_cast<size_t>(kCls) * kSlots * 16) * sizeof(int) + cells * sizeof(int) +
+         sizeof(StepCtrl);
 }
 
 ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
@@ -598,16 +679,23 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
   std::vector<int8_t> cellN;
+  int counts[kCls] = {0, 0, 0, 0, 0};
+  std::vector<int> cell_cls;
   if (pb->cell_degree) {
     cellN.resize(P.cells);
+    cell_cls.resize(P.cells);
     for (int c = 0; c < P.cells; ++c) {
       const int dg = pb->cell_degree[c];
       if (dg < 0 || dg > pb->degree) return fail(ctx, IPM_E_ARG, "cell_degree out of range");
       cellN[c] = static_cast<int8_t>(binom_basis(pb->p, dg));
+      cell_cls[c] = size_class(cellN[c] * P.M);
+      ++counts[cell_cls[c]];
     }
     P.uneven = true;
+  } else {
+    counts[size_class(P.M * P.N)] = P.cells;
   }
-  st = plan(ctx, P);
+  st = plan(ctx, P, counts);
   if (st != IPM_OK) return st;
 
   const size_t fp = ipm_problem_footprint(pb);
@@ -658,7 +746,10 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   ALLOC(P.d_ghost, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double));
   ALLOC(P.d_res, static_cast<size_t>(P.upd_blocks) * sizeof(double));
   ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long));
-  ALLOC(P.d_lists, 2 * static_cast<size_t>(kSlots) * P.list_cap * sizeof(int));
+  for (DualClass& D : P.cls) {
+    if (D.cap > 0) ALLOC(D.d_lists, 2 * static_cast<size_t>(kSlots) * D.cap * sizeof(int));
+    if (P.uneven && D.count > 0) ALLOC(D.d_order, static_cast<size_t>(D.count) * sizeof(int));
+  }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
   if (P.uneven) ALLOC(P.d_cellN, static_cast<size_t>(P.cells));
 #undef ALLOC
@@ -671,8 +762,15 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   } while (0)
   CHK(hipMemcpyAsync(P.d_phi, phip.data(), phip.size() * sizeof(double), hipMemcpyHostToDevice, s));
   CHK(hipMemcpyAsync(P.d_wphi, wphip.data(), wphip.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  if (P.uneven)
+  std::vector<std::vector<int>> orders(kCls);
+  if (P.uneven) {
     CHK(hipMemcpyAsync(P.d_cellN, cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
+    for (int c = 0; c < P.cells; ++c) orders[cell_cls[c]].push_back(c);
+    for (int k = 0; k < kCls; ++k)
+      if (P.cls[k].d_order)
+        CHK(hipMemcpyAsync(P.cls[k].d_order, orders[k].data(), orders[k].size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
   CHK(hipMemsetAsync(P.d_blk, 0, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long), s));
   CHK(hipMemsetAsync(P.d_res, 0, static_cast<size_t>(P.upd_blocks) * sizeof(double), s));
@@ -714,7 +812,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   {
     DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN, P.d_ctrl,
                                P.d_blk);
-    st = launch_dual(ctx, P, d, P.cells);
+    st = launch_dual_classes(ctx, P, d, false);
     if (st != IPM_OK) return cleanup(st);
   }
   // Dirichlet ghosts: fixed moments, converged dual, their nodal ansatz and speeds
@@ -751,7 +849,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     hipLaunchKernelGGL(pick_setup(P.M), dim3(1), dim3(256), 0, s, gp);
     CHK(hipGetLastError());
     DualParams d1 = dual_params(P, 1, 0, d_gu, d_gl, d_gn, nd, nullptr, d_gc, d_gb);
-    st = launch_dual(ctx, P, d1, nd);
+    st = launch_dual(ctx, P, d1, P.full_cls, false, nd);
     if (st != IPM_OK) return cleanup(st);
     for (int k = 0; k < nd; ++k)
       CHK(hipMemcpyAsync(P.d_ghost + dsides[k] * gq, d_gn + k * gq, gq * sizeof(double),

@@ -41,8 +41,8 @@ struct UpdateParams {
   double gamma, cfl, dx, dy, vol, t_end;
   double tau;
   int one_shot;
-  int* __restrict__ lists;           // [64][list_cap] Newton lists of the next step
-  int list_cap;
+  int* lists[kCls];                  // per size class: [64][list_cap] Newton lists of the next step
+  int list_cap[kCls];
   StepCtrl* ctrl;
   int parity;
 };
@@ -93,10 +93,10 @@ __device__ __forceinline__ void step_speeds(const StepCtrl* C, int parity, int d
 }
 
 template <int M, int G>
-__global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
+__device__ __forceinline__ void update_body(const UpdateParams& P, const int blk) {
   StepCtrl* C = P.ctrl;
   if (C->done[P.parity] || C->status) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
       C->done[P.parity ^ 1] = 1;
       C->t[P.parity ^ 1] = C->t[P.parity];
     }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
   const int lane = threadIdx.x & 63;
   const int gid = (threadIdx.x >> 6) * CPW + lane / G;
   const int r = lane % G;
-  const int cell = blockIdx.x * groups + gid;
+  const int cell = blk * groups + gid;
   double* ut = UT + static_cast<size_t>(gid) * Q * M;
   double* uq = UC + static_cast<size_t>(gid) * Q * M;
   double res_cell = 0.0, nx_speed = 0.0, ny_speed = 0.0;
@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
       double resn = 0.0;
 #pragma unroll
       for (int b = 0; b < M; ++b) resn += sqrt(group_sum<G>(gsq[b]));
-      route = (resn < 0.5 * P.tau) ? 0 : 1;  // NaN routes to Newton, which reports it
+      // NaN routes to Newton, which reports it; the value is the list class + 1
+      route = (resn < 0.5 * P.tau) ? 0 : 1 + size_class(Nc * M);
     }
   }
   // speeds of the cells whose nodal ansatz carries over to the next step
@@ -231,12 +232,12 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
     for (int k = 0; k < groups; ++k) {
       sres += red[2 * k];
       bad += red[2 * k + 1];
-      cnt += s_route[k];
+      cnt += s_route[k] ? 1 : 0;
     }
-    P.res_part[blockIdx.x] = sres;
+    P.res_part[blk] = sres;
     if (bad > 0.0 || !(ax == ax) || !(ay == ay) || !(dt > 0.0 || last))
       atomicOr(&C->status, kStNonfinite);
-    const int slot = blockIdx.x & (kSlots - 1);
+    const int slot = blk & (kSlots - 1);
     if (!P.one_shot) {
       double mx = 0.0, my = 0.0;
       for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
@@ -245,18 +246,22 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
       }
       atomicMax(&C->amax[P.parity ^ 1][0][slot * kSlotStride], speed_bits(mx));
       if (P.dim == 2) atomicMax(&C->amax[P.parity ^ 1][1][slot * kSlotStride], speed_bits(my));
-      int base = cnt ? static_cast<int>(atomicAdd(
-                           &C->list_len[(P.parity ^ 1) * kSlots * kSlotStride + slot * kSlotStride],
-                           static_cast<unsigned>(cnt)))
-                     : 0;
-      for (int k = 0; k < groups; ++k)
-        if (s_route[k]) {
-          if (base < P.list_cap)
-            P.lists[static_cast<size_t>(slot) * P.list_cap + base] = blockIdx.x * groups + k;
-          ++base;
+      if (cnt)
+        for (int c = 0; c < kCls; ++c) {
+          int cc = 0;
+          for (int k = 0; k < groups; ++k) cc += (s_route[k] == c + 1) ? 1 : 0;
+          if (!cc) continue;
+          int base = static_cast<int>(
+              atomicAdd(&C->list_len[list_len_index(P.parity ^ 1, c, slot)], static_cast<unsigned>(cc)));
+          for (int k = 0; k < groups; ++k)
+            if (s_route[k] == c + 1) {
+              if (base < P.list_cap[c])
+                P.lists[c][static_cast<size_t>(slot) * P.list_cap[c] + base] = blk * groups + k;
+              ++base;
+            }
         }
     }
-    if (blockIdx.x == 0) {
+    if (blk == 0) {
       C->t[P.parity ^ 1] = last ? P.t_end : t0 + dt;
       C->done[P.parity ^ 1] = last ? 1 : 0;
       C->dt_last = dt;
@@ -264,6 +269,18 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
       C->steps += 1;
     }
   }
+}
+
+template <int M, int G>
+__global__ __launch_bounds__(256) void update_kernel(UpdateParams P) {
+  update_body<M, G>(P, blockIdx.x);
+}
+
+template <int M, int G>
+__global__ __launch_bounds__(256) void update_batched(const UpdateParams* __restrict__ PP,
+                                                      const int* __restrict__ begin, int n) {
+  const int k = batch_problem(begin, n, blockIdx.x);
+  update_body<M, G>(PP[k], blockIdx.x - begin[k]);
 }
 
 // One block: residual of the last update (fixed summation order) and, for
