@@ -142,11 +142,28 @@ ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double *Phi, int
    IPM_E_NOMEM when the problem does not fit the HBM budget (admission). */
 ipm_status ipm_set_problem(ipm_ctx *ctx, const ipm_problem *pb, int *problem_id);
 
-/* Enqueue up to max_steps time steps for each of the n_ids problems.
-   Steps after a problem is done are skipped on the device.  If info is not
-   NULL the call waits and fills info[k] for ids[k]. */
+/* Enqueue up to max_steps time steps (Alg. 1 time loop; Alg. 2 pseudo-time
+   loop for one-shot problems) for each of the n_ids problems.  Steps after a
+   problem is done are skipped on the device.  With two or more distinct ids
+   the problems advance together: each step is one batched Newton launch per
+   kernel shape (all problems' cells of that shape) and one batched update
+   launch per shape, replayed from two device graphs (one per step parity)
+   that are built on the first call for this id list and reused while the
+   list and the problems' step counts match.  The results are those of
+   stepping each problem alone.  ids must be distinct (IPM_E_ARG).  If info is
+   not NULL the call waits and fills info[k] for ids[k]. */
 ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
                     ipm_step_info *info);
+
+/* Autotuner of the batched launches (no passage of the paper: a launch-shape
+   choice).  For every small-cell Newton kernel shape among the problems, runs
+   1 + steps_per_candidate real time steps of all n_ids problems with 1, 2 and
+   4 wavefronts per block, keeps the fastest and remembers it for problems of
+   the same shape created later in this context.  The choice does not change
+   any result (each cell's arithmetic is independent of the block shape); the
+   timed steps advance the problems.  *n_tuned (nullable) = shapes tuned. */
+ipm_status ipm_autotune(ipm_ctx *ctx, int n_ids, const int *ids, int steps_per_candidate,
+                        int *n_tuned);
 
 /* Wait for the context's stream and fill *info for one problem. */
 ipm_status ipm_query(ipm_ctx *ctx, int id, ipm_step_info *info);

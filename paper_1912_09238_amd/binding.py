@@ -61,7 +61,7 @@ class StepInfo(C.Structure):
 EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm_basis_table",
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
-           "ipm_last_error"]
+           "ipm_autotune", "ipm_last_error"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def load(path=None):
     lib.ipm_problem_footprint.restype = C.c_size_t
     lib.ipm_release.argtypes = [vp, C.c_int]
     lib.ipm_kernel_timing.argtypes = [vp, C.c_int, dp, dp, P(C.c_longlong)]
+    lib.ipm_autotune.argtypes = [vp, C.c_int, ip, C.c_int, ip]
     lib.ipm_last_error.argtypes = [vp]
     lib.ipm_last_error.restype = C.c_char_p
     _lib = lib
@@ -243,6 +244,15 @@ class Context:
 
     def release(self, pid):
         self._check(self.lib.ipm_release(self.h, pid))
+
+    def autotune(self, ids, steps_per_candidate=4):
+        """Pick the wavefronts per Newton block of every small-cell kernel shape
+        by timing real steps of the problems `ids` (see ipm_autotune)."""
+        ids = list(ids)
+        arr = (C.c_int * len(ids))(*ids)
+        n = C.c_int()
+        self._check(self.lib.ipm_autotune(self.h, len(ids), arr, int(steps_per_candidate), C.byref(n)))
+        return n.value
 
     def timing(self, enable):
         d, u, n = C.c_double(), C.c_double(), C.c_longlong()

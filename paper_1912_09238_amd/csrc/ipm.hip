@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -68,6 +69,46 @@ struct Problem {
   size_t upd_lds = 0;
 };
 
+// One launch of a batched step: a Newton launch of one kernel template over
+// several problems' size classes, an update launch over several problems, or
+// a single problem's steady-residual kernel.
+struct BatchLaunch {
+  int kind = 0;  // 0: Newton (batched), 1: update (batched), 2: residual
+  const void* fn = nullptr;
+  int blocks = 0, threads = 0;
+  size_t lds = 0;
+  size_t pofs = 0;  // first entry in the phase's params array of this kind
+  int bofs = 0;     // first entry in the begin array
+  int n = 0;        // problems (entries) in the launch
+  int pid = -1;     // residual: problem id
+  int parity = 0;   // residual: step parity
+};
+
+// Problems stepped together: both step parities prepared once, as launch
+// lists and as instantiated graphs.
+struct BatchPlan {
+  std::vector<int> ids;
+  std::vector<long long> step0;  // step_index of each problem when built
+  long long steps_done = 0;
+  unsigned long long gen = 0;    // context generation when built
+  std::vector<BatchLaunch> launches[2];
+  DualParams* d_dp = nullptr;    // [2][nd]
+  UpdateParams* d_up = nullptr;  // [2][nu]
+  int* d_begin = nullptr;
+  size_t nd = 0, nu = 0;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  ~BatchPlan() {
+    for (int k = 0; k < 2; ++k) {
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+    }
+    if (d_dp) (void)hipFree(d_dp);
+    if (d_up) (void)hipFree(d_up);
+    if (d_begin) (void)hipFree(d_begin);
+  }
+};
+
 }  // namespace
 
 struct ipm_ctx {
@@ -82,6 +123,9 @@ struct ipm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs: dual start/stop, update start/stop
   size_t ev_used = 0;
+  unsigned long long gen = 0;              // bumped when problems or launch shapes change
+  std::unique_ptr<BatchPlan> batch;        // cached plan of the last batched ipm_step
+  std::map<std::string, int> tuned_waves;  // autotuner: wavefronts per Newton block by shape
 };
 
 namespace {
@@ -260,6 +304,12 @@ void free_problem(Problem* P) {
   }
 }
 
+// shape key of a small-kernel class for the autotuner
+std::string tune_key(const Problem& P, const DualClass& D) {
+  return std::to_string(P.M) + "," + std::to_string(D.NP) + "," + std::to_string(P.Q) + "," +
+         std::to_string(P.kp);
+}
+
 // Launch geometry of a problem's kernels.  counts[c]: cells per size class.
 ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   const int n = P.M * P.N;
@@ -301,6 +351,10 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     if (D.T == 0) {
       D.waves = 4;
       while (D.waves > 1 && dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves) > 64 * 1024) D.waves >>= 1;
+      auto tw = ctx->tuned_waves.find(tune_key(P, D));
+      if (tw != ctx->tuned_waves.end() &&
+          dual_lds_bytes(P.M, D.NP, P.Q, P.kp, tw->second) <= ctx->max_lds)
+        D.waves = tw->second;
       D.lds = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves);
       // many nodes: the per-cell node buffers of a wavefront's cells do not
       // fit, so the class runs on the workgroup-per-cell kernel
@@ -318,7 +372,9 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
                                       std::to_string(P.Q) + ")");
     // list l receives the routed cells of update blocks b = l (mod 64)
     D.cap = D.count > 0 ? std::min(((P.upd_blocks + kSlots - 1) / kSlots) * ucpb, D.count) : 0;
-    const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
+    // block statistics sized for one wavefront per block, the smallest the
+    // autotuner may choose
+    const int per_block = D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP);
     const int items = std::max(kSlots * D.cap, D.count);
     D.blk_off = P.dual_blocks;
     D.blk_cnt = (items + per_block - 1) / per_block;
@@ -409,30 +465,7 @@ ipm_status launch_dual_classes(ipm_ctx* ctx, const Problem& P, const DualParams&
   return IPM_OK;
 }
 
-ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
-  const int parity = static_cast<int>(P.step_index & 1);
-  DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
-                             P.d_cellN, P.d_ctrl, P.d_blk);
-  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-  if (ctx->timing) {
-    while (ctx->ev.size() < ctx->ev_used + 4) {
-      hipEvent_t e;
-      HIPCHK(ctx, hipEventCreate(&e));
-      ctx->ev.push_back(e);
-    }
-    e0 = ctx->ev[ctx->ev_used];
-    e1 = ctx->ev[ctx->ev_used + 1];
-    e2 = ctx->ev[ctx->ev_used + 2];
-    e3 = ctx->ev[ctx->ev_used + 3];
-    ctx->ev_used += 4;
-    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
-  }
-  ipm_status st = launch_dual_classes(ctx, P, d, !P.one_shot);
-  if (st != IPM_OK) return st;
-  if (ctx->timing) {
-    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
-    HIPCHK(ctx, hipEventRecord(e2, ctx->stream));
-  }
+UpdateParams update_params(const Problem& P, int parity) {
   UpdateParams u{};
   u.wphi = P.d_wphi;
   u.N = P.N;
@@ -465,6 +498,34 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
     u.lists[c] = D.cap > 0 ? D.d_lists + static_cast<size_t>(parity ^ 1) * kSlots * D.cap : nullptr;
     u.list_cap[c] = D.cap;
   }
+  return u;
+}
+
+ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
+  const int parity = static_cast<int>(P.step_index & 1);
+  DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
+                             P.d_cellN, P.d_ctrl, P.d_blk);
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+  if (ctx->timing) {
+    while (ctx->ev.size() < ctx->ev_used + 4) {
+      hipEvent_t e;
+      HIPCHK(ctx, hipEventCreate(&e));
+      ctx->ev.push_back(e);
+    }
+    e0 = ctx->ev[ctx->ev_used];
+    e1 = ctx->ev[ctx->ev_used + 1];
+    e2 = ctx->ev[ctx->ev_used + 2];
+    e3 = ctx->ev[ctx->ev_used + 3];
+    ctx->ev_used += 4;
+    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+  }
+  ipm_status st = launch_dual_classes(ctx, P, d, !P.one_shot);
+  if (st != IPM_OK) return st;
+  if (ctx->timing) {
+    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(e2, ctx->stream));
+  }
+  UpdateParams u = update_params(P, parity);
   UpdFn fn = pick_update(P.M, P.UG);
   hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(256), P.upd_lds, ctx->stream, u);
   HIPCHK(ctx, hipGetLastError());
@@ -487,6 +548,285 @@ ipm_status enqueue_close(ipm_ctx* ctx, Problem& P) {
   return IPM_OK;
 }
 
+// ---------------------------------------------------------------- batching
+
+template <int M>
+const void* newton_batched_fn(int NP, int T) {
+  if (T > 0) {
+    if constexpr (16 % M == 0) {
+      switch (T) {
+        case 1: return reinterpret_cast<const void*>(newton_big_batched<M, 1>);
+        case 2: return reinterpret_cast<const void*>(newton_big_batched<M, 2>);
+        case 4: return reinterpret_cast<const void*>(newton_big_batched<M, 4>);
+        case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5>);
+        case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6>);
+        case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8>);
+        case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9>);
+      }
+    }
+    return nullptr;
+  }
+  switch (NP) {
+    case 8: return reinterpret_cast<const void*>(newton_batched<M, 8>);
+    case 16: return reinterpret_cast<const void*>(newton_batched<M, 16>);
+    case 32: return reinterpret_cast<const void*>(newton_batched<M, 32>);
+    case 64: return reinterpret_cast<const void*>(newton_batched<M, 64>);
+  }
+  return nullptr;
+}
+
+const void* pick_newton_batched(int M, int NP, int T) {
+  if (M == 1) return newton_batched_fn<1>(NP, T);
+  if (M == 3) return newton_batched_fn<3>(NP, T);
+  if (M == 4) return newton_batched_fn<4>(NP, T);
+  return nullptr;
+}
+
+template <int M>
+const void* update_batched_fn(int G) {
+  switch (G) {
+    case 16: return reinterpret_cast<const void*>(update_batched<M, 16>);
+    case 32: return reinterpret_cast<const void*>(update_batched<M, 32>);
+    case 64: return reinterpret_cast<const void*>(update_batched<M, 64>);
+  }
+  return nullptr;
+}
+
+const void* pick_update_batched(int M, int G) {
+  if (M == 1) return update_batched_fn<1>(G);
+  if (M == 3) return update_batched_fn<3>(G);
+  if (M == 4) return update_batched_fn<4>(G);
+  return nullptr;
+}
+
+// Build the launch lists of both step parities for the problems `ids`
+// (their next step and the one after), upload the parameter arrays and
+// instantiate one graph per parity.
+ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out) {
+  auto B = std::make_unique<BatchPlan>();
+  B->ids = ids;
+  B->gen = ctx->gen;
+  for (int id : ids) B->step0.push_back(get(ctx, id)->step_index);
+  struct NEntry {
+    DualParams d;
+    int blocks;
+    size_t lds;
+  };
+  struct UEntry {
+    UpdateParams u;
+    int blocks;
+    size_t lds;
+  };
+  std::vector<DualParams> dps;
+  std::vector<UpdateParams> ups;
+  std::vector<int> begins;
+  for (int ph = 0; ph < 2; ++ph) {
+    std::map<std::string, std::vector<NEntry>> ng;
+    std::map<std::string, std::pair<int, int>> nshape;  // key -> (threads, M)
+    std::map<std::string, const void*> nfn;
+    std::map<std::string, std::vector<UEntry>> ug;
+    std::map<std::string, const void*> ufn;
+    std::vector<BatchLaunch> resid;
+    for (int id : ids) {
+      Problem& P = *get(ctx, id);
+      const int parity = static_cast<int>((P.step_index + ph) & 1);
+      DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
+                                 P.d_cellN, P.d_ctrl, P.d_blk);
+      bool first = true;
+      for (int c = 0; c < kCls; ++c) {
+        const DualClass& D = P.cls[c];
+        if (D.count == 0) continue;
+        DualParams dc = d;
+        dc.cls = c;
+        dc.reset_next = first ? 1 : 0;
+        first = false;
+        dc.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+        int items;
+        if (!P.one_shot) {
+          dc.lists = D.d_lists + static_cast<size_t>(parity) * kSlots * D.cap;
+          dc.list_cap = D.cap;
+          items = kSlots * D.cap;
+        } else {
+          dc.list_cap = 0;
+          dc.order = D.d_order;
+          dc.order_len = D.count;
+          items = D.count;
+        }
+        const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
+        const int threads = D.T > 0 ? 256 : 64 * D.waves;
+        const std::string key = std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
+                                std::to_string(D.T) + ":" + std::to_string(threads);
+        ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
+        nshape[key] = {threads, P.M};
+        nfn[key] = pick_newton_batched(P.M, D.NP, D.T);
+        if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
+      }
+      const std::string ukey = std::to_string(P.M) + ":" + std::to_string(P.UG);
+      ug[ukey].push_back({update_params(P, parity), P.upd_blocks, P.upd_lds});
+      ufn[ukey] = pick_update_batched(P.M, P.UG);
+      if (P.steady_eps > 0.0) {
+        BatchLaunch L;
+        L.kind = 2;
+        L.pid = id;
+        L.parity = parity;
+        resid.push_back(L);
+      }
+    }
+    for (auto& kv : ng) {
+      BatchLaunch L;
+      L.kind = 0;
+      L.fn = nfn[kv.first];
+      L.threads = nshape[kv.first].first;
+      L.pofs = dps.size();
+      L.bofs = static_cast<int>(begins.size());
+      L.n = static_cast<int>(kv.second.size());
+      int acc = 0;
+      for (const NEntry& e : kv.second) {
+        dps.push_back(e.d);
+        begins.push_back(acc);
+        acc += e.blocks;
+        L.lds = std::max(L.lds, e.lds);
+      }
+      begins.push_back(acc);
+      L.blocks = acc;
+      if (acc > 0) B->launches[ph].push_back(L);
+    }
+    for (auto& kv : ug) {
+      BatchLaunch L;
+      L.kind = 1;
+      L.fn = ufn[kv.first];
+      if (!L.fn) return fail(ctx, IPM_E_ARG, "no batched update kernel for this size");
+      L.threads = 256;
+      L.pofs = ups.size();
+      L.bofs = static_cast<int>(begins.size());
+      L.n = static_cast<int>(kv.second.size());
+      int acc = 0;
+      for (const UEntry& e : kv.second) {
+        ups.push_back(e.u);
+        begins.push_back(acc);
+        acc += e.blocks;
+        L.lds = std::max(L.lds, e.lds);
+      }
+      begins.push_back(acc);
+      L.blocks = acc;
+      if (acc > 0) B->launches[ph].push_back(L);
+    }
+    for (const BatchLaunch& L : resid) B->launches[ph].push_back(L);
+  }
+  B->nd = dps.size();
+  B->nu = ups.size();
+  HIPCHK(ctx, hipMalloc(&B->d_dp, std::max<size_t>(dps.size(), 1) * sizeof(DualParams)));
+  HIPCHK(ctx, hipMalloc(&B->d_up, std::max<size_t>(ups.size(), 1) * sizeof(UpdateParams)));
+  HIPCHK(ctx, hipMalloc(&B->d_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
+  HIPCHK(ctx, hipMemcpyAsync(B->d_dp, dps.data(), dps.size() * sizeof(DualParams),
+                             hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(B->d_up, ups.data(), ups.size() * sizeof(UpdateParams),
+                             hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(B->d_begin, begins.data(), begins.size() * sizeof(int),
+                             hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  // one graph per parity: Newton launches in parallel, then the updates,
+  // then the steady residuals
+  for (int ph = 0; ph < 2; ++ph) {
+    HIPCHK(ctx, hipGraphCreate(&B->graph[ph], 0));
+    std::vector<hipGraphNode_t> newton, update;
+    for (const BatchLaunch& L : B->launches[ph]) {
+      hipKernelNodeParams kp{};
+      kp.gridDim = dim3(L.blocks);
+      kp.blockDim = dim3(L.threads);
+      kp.sharedMemBytes = static_cast<unsigned>(L.lds);
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      if (L.kind == 0 || L.kind == 1) {
+        const void* pp = L.kind == 0 ? static_cast<const void*>(B->d_dp + L.pofs)
+                                     : static_cast<const void*>(B->d_up + L.pofs);
+        const int* bg = B->d_begin + L.bofs;
+        int n = L.n;
+        void* args[3] = {&pp, &bg, &n};
+        kp.func = const_cast<void*>(L.fn);
+        kp.kernelParams = args;
+        const std::vector<hipGraphNode_t> none;
+        const std::vector<hipGraphNode_t>& deps = L.kind == 0 ? none : newton;
+        HIPCHK(ctx, hipGraphAddKernelNode(&node, B->graph[ph], deps.data(), deps.size(), &kp));
+        (L.kind == 0 ? newton : update).push_back(node);
+      } else {
+        const Problem& P = *get(ctx, L.pid);
+        StepCtrl* C = P.d_ctrl;
+        const double* rp = P.d_res;
+        int nparts = P.upd_blocks;
+        double eps = P.steady_eps;
+        int par = L.parity;
+        const unsigned long long* bs = P.d_blk;
+        int nblk = P.dual_blocks, close = 0;
+        void* args[8] = {&C, &rp, &nparts, &eps, &par, &bs, &nblk, &close};
+        kp.func = reinterpret_cast<void*>(residual_kernel);
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(256);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        HIPCHK(ctx, hipGraphAddKernelNode(&node, B->graph[ph], update.data(), update.size(), &kp));
+      }
+    }
+    HIPCHK(ctx, hipGraphInstantiate(&B->exec[ph], B->graph[ph], nullptr, nullptr, 0));
+  }
+  out = std::move(B);
+  return IPM_OK;
+}
+
+bool batch_valid(const ipm_ctx* ctx, const BatchPlan* B, const std::vector<int>& ids) {
+  if (!B || B->gen != ctx->gen || B->ids != ids) return false;
+  for (size_t k = 0; k < ids.size(); ++k) {
+    const Problem* P = ctx->problems[ids[k]].get();
+    if (!P || P->step_index != B->step0[k] + B->steps_done) return false;
+  }
+  return true;
+}
+
+// `steps` batched steps: graph replays, or launch by launch with events
+// around the Newton and update phases when kernel timing is on
+ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
+  for (int s = 0; s < steps; ++s) {
+    const int ph = static_cast<int>(B.steps_done & 1);
+    if (!ctx->timing) {
+      HIPCHK(ctx, hipGraphLaunch(B.exec[ph], ctx->stream));
+    } else {
+      while (ctx->ev.size() < ctx->ev_used + 4) {
+        hipEvent_t e;
+        HIPCHK(ctx, hipEventCreate(&e));
+        ctx->ev.push_back(e);
+      }
+      hipEvent_t* e = &ctx->ev[ctx->ev_used];
+      ctx->ev_used += 4;
+      HIPCHK(ctx, hipEventRecord(e[0], ctx->stream));
+      int phase_kind = 0;
+      for (const BatchLaunch& L : B.launches[ph]) {
+        if (L.kind != 0 && phase_kind == 0) {
+          HIPCHK(ctx, hipEventRecord(e[1], ctx->stream));
+          HIPCHK(ctx, hipEventRecord(e[2], ctx->stream));
+          phase_kind = 1;
+        }
+        if (L.kind == 0 || L.kind == 1) {
+          const void* pp = L.kind == 0 ? static_cast<const void*>(B.d_dp + L.pofs)
+                                       : static_cast<const void*>(B.d_up + L.pofs);
+          const int* bg = B.d_begin + L.bofs;
+          int n = L.n;
+          void* args[3] = {&pp, &bg, &n};
+          HIPCHK(ctx, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.threads), args, L.lds, ctx->stream));
+        } else {
+          const Problem& P = *get(ctx, L.pid);
+          hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
+                             P.upd_blocks, P.steady_eps, L.parity, P.d_blk, P.dual_blocks, 0);
+          HIPCHK(ctx, hipGetLastError());
+        }
+      }
+      HIPCHK(ctx, hipEventRecord(e[3], ctx->stream));
+    }
+    ++B.steps_done;
+    for (int id : B.ids) ++get(ctx, id)->step_index;
+  }
+  return IPM_OK;
+}
+
 ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   static bool done = false;
   if (done) return IPM_OK;
@@ -501,9 +841,20 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
   for (int M : {1, 4})
-    for (int T : {1, 2, 4, 5, 6, 8, 9})
+    for (int T : {1, 2, 4, 5, 6, 8, 9}) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    }
+  for (int M : {1, 3, 4}) {
+    for (int NP : {8, 16, 32, 64})
+      (void)hipFuncSetAttribute(pick_newton_batched(M, NP, 0),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    for (int G : {16, 32, 64})
+      (void)hipFuncSetAttribute(pick_update_batched(M, G),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  }
 
   (void)hipGetLastError();  // the request is best effort; do not leave a sticky error
   done = true;
@@ -636,6 +987,7 @@ ipm_status ipm_destroy(ipm_ctx* ctx) {
   if (!ctx) return IPM_E_ARG;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->batch.reset();
   for (auto& p : ctx->problems) free_problem(p.get());
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -890,6 +1242,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   CHK(hipStreamSynchronize(s));
 #undef CHK
   ctx->used += P.bytes;
+  ++ctx->gen;
   ctx->problems[slot] = std::move(up);
   *problem_id = slot;
   return IPM_OK;
@@ -902,11 +1255,28 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
   for (int k = 0; k < n_ids; ++k)
     if (!get(ctx, ids[k])) return fail(ctx, IPM_E_STATE, "ipm_step: unknown problem id");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  for (int s = 0; s < max_steps; ++s)
-    for (int k = 0; k < n_ids; ++k) {
-      ipm_status st = enqueue_step(ctx, *get(ctx, ids[k]));
+  if (n_ids >= 2 && max_steps > 0) {
+    // several problems: batched launches per kernel shape, replayed as graphs
+    std::vector<int> v(ids, ids + n_ids);
+    for (size_t a = 0; a < v.size(); ++a)
+      for (size_t b = a + 1; b < v.size(); ++b)
+        if (v[a] == v[b]) return fail(ctx, IPM_E_ARG, "ipm_step: repeated problem id");
+    if (!batch_valid(ctx, ctx->batch.get(), v)) {
+      // the old plan's graphs may still be queued: drain before freeing
+      if (ctx->batch) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      ctx->batch.reset();
+      ipm_status st = build_batch(ctx, v, ctx->batch);
       if (st != IPM_OK) return st;
     }
+    ipm_status st = run_batch(ctx, *ctx->batch, max_steps);
+    if (st != IPM_OK) return st;
+  } else {
+    for (int s = 0; s < max_steps; ++s)
+      for (int k = 0; k < n_ids; ++k) {
+        ipm_status st = enqueue_step(ctx, *get(ctx, ids[k]));
+        if (st != IPM_OK) return st;
+      }
+  }
   if (max_steps > 0)
     for (int k = 0; k < n_ids; ++k) {
       ipm_status st = enqueue_close(ctx, *get(ctx, ids[k]));
@@ -987,8 +1357,83 @@ ipm_status ipm_release(ipm_ctx* ctx, int id) {
   if (!P) return fail(ctx, IPM_E_STATE, "ipm_release: unknown problem id");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->used -= std::min(ctx->used, P->bytes);
+  ++ctx->gen;
+  ctx->batch.reset();
   free_problem(P);
   ctx->problems[id].reset();
+  return IPM_OK;
+}
+
+ipm_status ipm_autotune(ipm_ctx* ctx, int n_ids, const int* ids, int steps_per_candidate,
+                        int* n_tuned) {
+  if (!ctx) return IPM_E_ARG;
+  if (n_ids <= 0 || !ids || steps_per_candidate <= 0)
+    return fail(ctx, IPM_E_ARG, "ipm_autotune: bad arguments");
+  for (int k = 0; k < n_ids; ++k)
+    if (!get(ctx, ids[k])) return fail(ctx, IPM_E_STATE, "ipm_autotune: unknown problem id");
+  if (ctx->timing) return fail(ctx, IPM_E_STATE, "ipm_autotune: kernel timing is on");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  // small-kernel classes by shape
+  std::map<std::string, std::vector<std::pair<Problem*, int>>> shapes;
+  for (int k = 0; k < n_ids; ++k) {
+    Problem* P = get(ctx, ids[k]);
+    for (int c = 0; c < kCls; ++c)
+      if (P->cls[c].count > 0 && P->cls[c].T == 0) shapes[tune_key(*P, P->cls[c])].push_back({P, c});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  int tuned = 0;
+  ipm_status st = IPM_OK;
+  for (auto& kv : shapes) {
+    const Problem* P0 = kv.second.front().first;
+    const DualClass& D0 = P0->cls[kv.second.front().second];
+    int best = D0.waves;
+    float best_ms = -1.f;
+    for (int w : {1, 2, 4}) {
+      const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, P0->kp, w);
+      if (lds > ctx->max_lds) continue;
+      for (auto& pc : kv.second) {
+        pc.first->cls[pc.second].waves = w;
+        pc.first->cls[pc.second].lds = lds;
+      }
+      ++ctx->gen;
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        st = IPM_E_DEVICE;
+        break;
+      }
+      ctx->batch.reset();
+      // one untimed step builds the plan and warms the kernels
+      if ((st = ipm_step(ctx, n_ids, ids, 1, nullptr)) != IPM_OK) break;
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = IPM_E_DEVICE; break; }
+      if ((st = ipm_step(ctx, n_ids, ids, steps_per_candidate, nullptr)) != IPM_OK) break;
+      if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = IPM_E_DEVICE;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms < 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = w;
+      }
+    }
+    if (st != IPM_OK) break;
+    const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, P0->kp, best);
+    for (auto& pc : kv.second) {
+      pc.first->cls[pc.second].waves = best;
+      pc.first->cls[pc.second].lds = lds;
+    }
+    ctx->tuned_waves[kv.first] = best;
+    ++tuned;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ++ctx->gen;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->batch.reset();
+  if (st != IPM_OK) return st == IPM_E_DEVICE ? fail(ctx, st, "ipm_autotune: device error") : st;
+  if (n_tuned) *n_tuned = tuned;
   return IPM_OK;
 }
 
