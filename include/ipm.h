@@ -155,6 +155,19 @@ ipm_status ipm_set_problem(ipm_ctx *ctx, const ipm_problem *pb, int *problem_id)
 ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
                     ipm_step_info *info);
 
+/* Static per-cell total degree for the batching form (Sec. 5: the first
+   entry of the smoothness indicator eq:errorIndicator, computed from the
+   first conserved variable's moments at t = 0).  Levels are total degrees
+   1..max_degree; a cell gets the highest level l >= 2 whose indicator
+   S_l = <(u_l - u_{l-1})^2> / <u_l^2> exceeds delta_hi, else 1 (a static
+   reading of the raise rule, with the thresholds ordered as delta_lo <
+   delta_hi).  ic_nodal: host [cells][Q][m] values u_IC(x_j, xi_q) on the
+   tensor rule of quad_per_dim points (quad_per_dim >= max_degree + 1, so
+   that the averages are exact sums of squared modes).  out_degree: host
+   [cells].  Needs no context and no device; errors: IPM_E_ARG. */
+ipm_status ipm_select_degrees(int p, int max_degree, int quad_per_dim, int m, int cells,
+                              const double *ic_nodal, double delta_hi, int8_t *out_degree);
+
 /* Autotuner of the batched launches (no passage of the paper: a launch-shape
    choice).  For every small-cell Newton kernel shape among the problems, runs
    1 + steps_per_candidate real time steps of all n_ids problems with 1, 2 and

@@ -166,6 +166,67 @@ void orc_basis_eval(int p, int degree, int Q, const double *nodes, double *Phi)
   free(idx);
 }
 
+/* eq:errorIndicator: the truncations u_l are evaluated at the nodes and the
+   averages are quadrature sums, exactly as the definition reads. */
+void orc_indicator(int p, int L, int qpd, const double *u_nodes, double *S)
+{
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= qpd;
+  double *nodes = (double *)malloc(sizeof(double) * Q * p);
+  double *w = (double *)malloc(sizeof(double) * Q);
+  orc_quadrature(p, qpd, nodes, w);
+  int N = orc_num_basis(p, L);
+  double *Phi = (double *)malloc(sizeof(double) * Q * N);
+  double *uh = (double *)malloc(sizeof(double) * N);
+  double *prev = (double *)malloc(sizeof(double) * Q);
+  double *cur = (double *)malloc(sizeof(double) * Q);
+  orc_basis_eval(p, L, Q, nodes, Phi);
+  for (int i = 0; i < N; ++i) {
+    double a = 0.0;
+    for (int q = 0; q < Q; ++q) a += w[q] * u_nodes[q] * Phi[q * N + i];
+    uh[i] = a;
+  }
+  for (int q = 0; q < Q; ++q) prev[q] = uh[0] * Phi[q * N];  /* u_0 */
+  for (int l = 1; l <= L; ++l) {
+    int Nl = orc_num_basis(p, l);
+    double num = 0.0, den = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      double v = 0.0;
+      for (int i = 0; i < Nl; ++i) v += uh[i] * Phi[q * N + i];
+      cur[q] = v;
+      num += w[q] * (v - prev[q]) * (v - prev[q]);
+      den += w[q] * v * v;
+    }
+    S[l - 1] = num / den;
+    for (int q = 0; q < Q; ++q) prev[q] = cur[q];
+  }
+  free(nodes);
+  free(w);
+  free(Phi);
+  free(uh);
+  free(prev);
+  free(cur);
+}
+
+void orc_select_degrees(int p, int L, int qpd, int m, int cells, const double *ic_nodal,
+                        double delta_hi, signed char *out)
+{
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= qpd;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < cells; ++c) {
+    double u[1024], S[16];
+    double *uu = Q <= (int)(sizeof(u) / sizeof(u[0])) ? u : (double *)malloc(sizeof(double) * Q);
+    for (int q = 0; q < Q; ++q) uu[q] = ic_nodal[((size_t)c * Q + q) * m];
+    orc_indicator(p, L, qpd, uu, S);
+    int lev = 1;
+    for (int l = 2; l <= L; ++l)
+      if (S[l - 1] > delta_hi) lev = l;
+    out[c] = (signed char)lev;
+    if (uu != u) free(uu);
+  }
+}
+
 /* ------------------------------------------------------------------ */
 /* Closures u_s = (grad s)^-1, its Jacobian, s_* (Sec. 2 eq:ansatz,     */
 /* Sec. 3.1; App. B for Euler)                                          */

@@ -75,6 +75,19 @@ int orc_quadrature(int p, int qpd, double *nodes /*[Q][p]*/, double *w /*[Q], su
 int orc_multi_indices(int p, int degree, int *idx /*[N][p]*/);
 void orc_basis_eval(int p, int degree, int Q, const double *nodes, double *Phi /*[Q][N]*/);
 
+/* Smoothness indicator of Sec. 5 (eq:errorIndicator) for one scalar field
+   given at the Q nodes: moments up to total degree L by quadrature, then for
+   levels l = 1..L (level l = total degree l)
+     S[l-1] = <(u_l - u_{l-1})^2>_Q / <u_l^2>_Q,  u_l = sum_{|i|<=l} u_i phi_i,
+   with every average taken by the quadrature rule. */
+void orc_indicator(int p, int L, int qpd, const double *u_nodes /*[Q]*/, double *S /*[L]*/);
+
+/* Static per-cell level at t = 0 (first entry of the indicator: the first
+   conserved variable): the highest level l >= 2 with S_l > delta_hi, else 1.
+   ic_nodal [cells][Q][m]; out [cells] total degree in 1..L. */
+void orc_select_degrees(int p, int L, int qpd, int m, int cells, const double *ic_nodal,
+                        double delta_hi, signed char *out);
+
 /* closures at one node; m = 1 (scalar) or d+2 (Euler) */
 int orc_closure(int entropy, int m, double gamma, double um, double up,
                 const double *Lam, double *u, double *J /*[m][m]*/, double *sstar);

@@ -74,6 +74,10 @@ def load():
     lib.orc_multi_indices.argtypes = [i, i, ip]
     lib.orc_basis_eval.argtypes = [i, i, i, dp, dp]
     lib.orc_basis_eval.restype = None
+    lib.orc_indicator.argtypes = [i, i, i, dp, dp]
+    lib.orc_indicator.restype = None
+    lib.orc_select_degrees.argtypes = [i, i, i, i, i, dp, d, P(C.c_byte)]
+    lib.orc_select_degrees.restype = None
     lib.orc_closure.argtypes = [i, i, d, d, d, dp, dp, dp, dp]
     lib.orc_entropy_grad.argtypes = [i, i, d, d, d, dp, dp]
     lib.orc_entropy.argtypes = [i, i, d, d, d, dp]
@@ -136,6 +140,25 @@ def basis_eval(p, degree, nodes):
     Phi = np.zeros((nodes.shape[0], num_basis(p, degree)))
     load().orc_basis_eval(p, degree, nodes.shape[0], _ptr(nodes), _ptr(Phi))
     return Phi
+
+
+def indicator(p, L, qpd, u_nodes):
+    """S_1..S_L of eq:errorIndicator for one scalar field at the Q nodes."""
+    u = np.ascontiguousarray(u_nodes, dtype=np.float64).reshape(-1)
+    S = np.zeros(L)
+    load().orc_indicator(p, L, qpd, _ptr(u), _ptr(S))
+    return S
+
+
+def select_degrees(p, L, qpd, ic_nodal, delta_hi=1e-4):
+    """Static per-cell total degree (1..L) from the indicator of the first
+    conserved variable; ic_nodal [cells][Q][m]."""
+    ic = np.ascontiguousarray(ic_nodal, dtype=np.float64)
+    cells, Q, m = ic.shape
+    out = np.zeros(cells, dtype=np.int8)
+    load().orc_select_degrees(p, L, qpd, m, cells, _ptr(ic), float(delta_hi),
+                              out.ctypes.data_as(C.POINTER(C.c_byte)))
+    return out
 
 
 def closure(entropy, m, Lam, gamma=1.4, um=0.0, up=1.0):

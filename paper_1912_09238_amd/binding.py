@@ -61,7 +61,7 @@ class StepInfo(C.Structure):
 EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm_basis_table",
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
-           "ipm_autotune", "ipm_last_error"]
+           "ipm_select_degrees", "ipm_autotune", "ipm_last_error"]
 
 _lib = None
 
@@ -92,6 +92,8 @@ def load(path=None):
     lib.ipm_release.argtypes = [vp, C.c_int]
     lib.ipm_kernel_timing.argtypes = [vp, C.c_int, dp, dp, P(C.c_longlong)]
     lib.ipm_autotune.argtypes = [vp, C.c_int, ip, C.c_int, ip]
+    lib.ipm_select_degrees.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double,
+                                       P(C.c_int8)]
     lib.ipm_last_error.argtypes = [vp]
     lib.ipm_last_error.restype = C.c_char_p
     _lib = lib
@@ -120,6 +122,20 @@ def basis_table(p, degree, qpd):
     if st != 0:
         raise IpmError(st, lib.ipm_last_error(None).decode())
     return Phi
+
+
+def select_degrees(p, max_degree, qpd, ic_nodal, delta_hi=1e-4):
+    """Per-cell total degree 1..max_degree from the smoothness indicator of
+    the first conserved variable (ipm_select_degrees); ic_nodal [cells][Q][m]."""
+    lib = load()
+    ic = np.ascontiguousarray(ic_nodal, dtype=np.float64)
+    cells, _, m = ic.shape
+    out = np.zeros(cells, dtype=np.int8)
+    st = lib.ipm_select_degrees(p, max_degree, qpd, m, cells, _dptr(ic), float(delta_hi),
+                                out.ctypes.data_as(C.POINTER(C.c_int8)))
+    if st != 0:
+        raise IpmError(st, lib.ipm_last_error(None).decode())
+    return out
 
 
 def problem_struct(spec, keep):

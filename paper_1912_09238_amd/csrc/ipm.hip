@@ -1364,6 +1364,44 @@ ipm_status ipm_release(ipm_ctx* ctx, int id) {
   return IPM_OK;
 }
 
+ipm_status ipm_select_degrees(int p, int max_degree, int quad_per_dim, int m, int cells,
+                              const double* ic_nodal, double delta_hi, int8_t* out_degree) {
+  if (p < 1 || p > 3 || max_degree < 1 || max_degree > 20 || m < 1 || m > 4 || cells < 0 ||
+      (cells > 0 && (!ic_nodal || !out_degree)) || !(delta_hi >= 0.0))
+    return fail(nullptr, IPM_E_ARG, "ipm_select_degrees: bad arguments");
+  if (quad_per_dim < max_degree + 1)
+    return fail(nullptr, IPM_E_ARG,
+                "ipm_select_degrees: needs quad_per_dim >= max_degree + 1 (exact mode sums)");
+  std::vector<double> nodes, w;
+  const int Q = tensor_rule(p, quad_per_dim, nodes, w);
+  const int N = binom_basis(p, max_degree);
+  const std::vector<double> phi = basis_table(p, max_degree, Q, nodes);
+  std::vector<int> first(max_degree + 2);  // modes of total degree l: [first[l], first[l+1])
+  for (int l = 0; l <= max_degree + 1; ++l) first[l] = l == 0 ? 0 : binom_basis(p, l - 1);
+  std::vector<double> uh(N);
+  for (int c = 0; c < cells; ++c) {
+    // moments of the first conserved variable (Alg. 1 first loop)
+    for (int i = 0; i < N; ++i) {
+      double a = 0.0;
+      for (int q = 0; q < Q; ++q)
+        a += w[q] * ic_nodal[(static_cast<size_t>(c) * Q + q) * m] * phi[static_cast<size_t>(q) * N + i];
+      uh[i] = a;
+    }
+    // eq:errorIndicator with an orthonormal basis: <(u_l - u_{l-1})^2> is the
+    // sum of squares of the degree-l modes, <u_l^2> that of all modes <= l
+    int level = 1;
+    double den = uh[0] * uh[0];
+    for (int l = 1; l <= max_degree; ++l) {
+      double num = 0.0;
+      for (int i = first[l]; i < first[l + 1]; ++i) num += uh[i] * uh[i];
+      den += num;
+      if (l >= 2 && num / den > delta_hi) level = l;
+    }
+    out_degree[c] = static_cast<int8_t>(level);
+  }
+  return IPM_OK;
+}
+
 ipm_status ipm_autotune(ipm_ctx* ctx, int n_ids, const int* ids, int steps_per_candidate,
                         int* n_tuned) {
   if (!ctx) return IPM_E_ARG;
