@@ -116,6 +116,20 @@ typedef struct {
   int max_iters;            /* largest Newton count of one cell in one step */
 } ipm_step_info;
 
+/* One request of the serving loop (ipm_serve). */
+typedef struct {
+  const ipm_problem *problem; /* the solve; inputs must stay valid until it is admitted */
+  double arrival_s;         /* arrival, seconds after ipm_serve starts */
+  double *moments_out;      /* host [cells][m][N], written when it finishes (nullable) */
+  size_t moments_len;       /* capacity of moments_out in doubles */
+  /* filled by ipm_serve: */
+  double admitted_s;        /* when its state was set up on the device (-1: never) */
+  double finished_s;        /* when its moments were back on the host */
+  long long steps;          /* completed time steps */
+  int status;               /* ipm_status of the request */
+  int reserved;
+} ipm_request;
+
 /* Create a context on cfg->device.  *out receives the handle. */
 ipm_status ipm_create(const ipm_config *cfg, ipm_ctx **out);
 
@@ -167,6 +181,20 @@ ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
    [cells].  Needs no context and no device; errors: IPM_E_ARG. */
 ipm_status ipm_select_degrees(int p, int max_degree, int quad_per_dim, int m, int cells,
                               const double *ic_nodal, double delta_hi, int8_t *out_degree);
+
+/* Serving loop (a runtime around the method; no passage of the paper).  Runs
+   the n requests against the wall clock: a request is admitted once it has
+   arrived, fewer than max_active requests are on the device and its state
+   fits the context's HBM budget (ipm_set_problem's IPM_E_NOMEM is the
+   admission signal; a request that cannot fit even alone fails with it).
+   Admitted requests keep their moment and dual state resident and advance
+   together, steps_per_round batched time steps per round (ipm_step with all
+   active ids); new requests join at round boundaries and finished ones leave
+   (moments copied to moments_out, state released).  Every request's result
+   equals that of stepping it alone.  Blocks until every request finished or
+   failed; per-request failures are reported in reqs[k].status, the return
+   value only reports device or argument errors. */
+ipm_status ipm_serve(ipm_ctx *ctx, int n, ipm_request *reqs, int steps_per_round, int max_active);
 
 /* Autotuner of the batched launches (no passage of the paper: a launch-shape
    choice).  For every small-cell Newton kernel shape among the problems, runs

@@ -58,10 +58,17 @@ class StepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Request(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("arrival_s", C.c_double),
+                ("moments_out", C.POINTER(C.c_double)), ("moments_len", C.c_size_t),
+                ("admitted_s", C.c_double), ("finished_s", C.c_double), ("steps", C.c_longlong),
+                ("status", C.c_int), ("reserved", C.c_int)]
+
+
 EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm_basis_table",
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
-           "ipm_select_degrees", "ipm_autotune", "ipm_last_error"]
+           "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_last_error"]
 
 _lib = None
 
@@ -92,6 +99,7 @@ def load(path=None):
     lib.ipm_release.argtypes = [vp, C.c_int]
     lib.ipm_kernel_timing.argtypes = [vp, C.c_int, dp, dp, P(C.c_longlong)]
     lib.ipm_autotune.argtypes = [vp, C.c_int, ip, C.c_int, ip]
+    lib.ipm_serve.argtypes = [vp, C.c_int, P(Request), C.c_int, C.c_int]
     lib.ipm_select_degrees.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double,
                                        P(C.c_int8)]
     lib.ipm_last_error.argtypes = [vp]
@@ -197,9 +205,9 @@ class Context:
         except Exception:
             pass
 
-    def set_problem(self, spec, ic_nodal=None, ic_moments=None, ic_dual=None, dirichlet=None,
-                    cell_degree=None):
-        keep = []
+    @staticmethod
+    def _problem(spec, keep, ic_nodal=None, ic_moments=None, ic_dual=None, dirichlet=None,
+                 cell_degree=None):
         pb = problem_struct(spec, keep)
 
         def arr(a):
@@ -217,9 +225,49 @@ class Context:
             cd = np.ascontiguousarray(cell_degree, dtype=np.int8)
             keep.append(cd)
             pb.cell_degree = cd.ctypes.data_as(C.POINTER(C.c_int8))
+        keep.append(pb)
+        return pb
+
+    def set_problem(self, spec, ic_nodal=None, ic_moments=None, ic_dual=None, dirichlet=None,
+                    cell_degree=None):
+        keep = []
+        pb = self._problem(spec, keep, ic_nodal, ic_moments, ic_dual, dirichlet, cell_degree)
         pid = C.c_int(-1)
         self._check(self.lib.ipm_set_problem(self.h, C.byref(pb), C.byref(pid)))
         return pid.value
+
+    def serve(self, requests, steps_per_round=8, max_active=64, moments=True):
+        """Run a request stream through ipm_serve.  requests: list of dicts with
+        'spec', 'arrival' (s) and the set_problem keyword arrays ('ic_nodal',
+        ...).  Returns one dict per request: admitted, finished, latency,
+        steps, status and (if moments) the final moments."""
+        keep = []
+        reqs = (Request * len(requests))()
+        outs = []
+        for k, rq in enumerate(requests):
+            kw = {key: rq.get(key) for key in ("ic_nodal", "ic_moments", "ic_dual", "dirichlet",
+                                               "cell_degree")}
+            pb = self._problem(rq["spec"], keep, **kw)
+            reqs[k].problem = C.cast(C.pointer(pb), C.c_void_p)
+            reqs[k].arrival_s = float(rq["arrival"])
+            out = None
+            if moments:
+                m = {"burgers1d": 1, "euler1d": 3, "euler2d": 4}[rq["spec"]["equation"]]
+                cells = rq["spec"]["nx"] * (rq["spec"].get("ny", 1) if m == 4 else 1)
+                N = self.lib.ipm_basis_size(rq["spec"]["p"], rq["spec"]["degree"])
+                out = np.zeros((cells, m, N))
+                reqs[k].moments_out = _dptr(out)
+                reqs[k].moments_len = out.size
+            outs.append(out)
+        self._check(self.lib.ipm_serve(self.h, len(requests), reqs, int(steps_per_round),
+                                       int(max_active)))
+        res = []
+        for k, rq in enumerate(requests):
+            r = reqs[k]
+            res.append({"admitted": r.admitted_s, "finished": r.finished_s,
+                        "latency": r.finished_s - r.arrival_s, "steps": r.steps,
+                        "status": r.status, "moments": outs[k]})
+        return res
 
     def footprint(self, spec):
         return self.lib.ipm_problem_footprint(C.byref(problem_struct(spec, [])))

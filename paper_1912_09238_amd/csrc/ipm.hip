@@ -7,12 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ipm.h"
@@ -64,7 +66,8 @@ struct Problem {
   int8_t* d_cellN = nullptr;
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
-  size_t bytes = 0;
+  size_t bytes = 0;    // device bytes allocated
+  size_t charged = 0;  // bytes charged against the context's budget
   int upd_blocks = 1, dual_blocks = 1;
   size_t upd_lds = 0;
 };
@@ -1241,7 +1244,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   CHK(hipMemcpyAsync(&P.d_ctrl->ghost_amax[0], gam, sizeof(gam), hipMemcpyHostToDevice, s));
   CHK(hipStreamSynchronize(s));
 #undef CHK
-  ctx->used += P.bytes;
+  P.charged = std::max(fp, P.bytes);
+  ctx->used += P.charged;
   ++ctx->gen;
   ctx->problems[slot] = std::move(up);
   *problem_id = slot;
@@ -1356,11 +1360,97 @@ ipm_status ipm_release(ipm_ctx* ctx, int id) {
   Problem* P = get(ctx, id);
   if (!P) return fail(ctx, IPM_E_STATE, "ipm_release: unknown problem id");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  ctx->used -= std::min(ctx->used, P->bytes);
+  ctx->used -= std::min(ctx->used, P->charged);
   ++ctx->gen;
   ctx->batch.reset();
   free_problem(P);
   ctx->problems[id].reset();
+  return IPM_OK;
+}
+
+ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round, int max_active) {
+  if (!ctx) return IPM_E_ARG;
+  if (n < 0 || (n > 0 && !reqs) || steps_per_round < 1 || max_active < 1)
+    return fail(ctx, IPM_E_ARG, "ipm_serve: bad arguments");
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) {
+    order[k] = k;
+    reqs[k].admitted_s = -1.0;
+    reqs[k].finished_s = -1.0;
+    reqs[k].steps = 0;
+    reqs[k].status = IPM_OK;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+  size_t next = 0;
+  int finished = 0;
+  std::vector<int> active_req, active_id;
+  std::vector<StepCtrl> ctrl;
+  while (finished < n) {
+    // admission, in arrival order, while slots and HBM budget allow
+    while (next < order.size() && reqs[order[next]].arrival_s <= now_s() &&
+           static_cast<int>(active_req.size()) < max_active) {
+      ipm_request& R = reqs[order[next]];
+      int pid = -1;
+      ipm_status st = R.problem ? ipm_set_problem(ctx, R.problem, &pid) : IPM_E_ARG;
+      if (st == IPM_E_NOMEM && !active_req.empty()) break;  // wait for memory to free up
+      ++next;
+      if (st != IPM_OK) {
+        if (st == IPM_E_DEVICE) return st;
+        R.status = st;
+        R.finished_s = now_s();
+        ++finished;
+        continue;
+      }
+      R.admitted_s = now_s();
+      active_req.push_back(order[next - 1]);
+      active_id.push_back(pid);
+    }
+    if (active_req.empty()) {
+      if (next < order.size()) {
+        const double wait = reqs[order[next]].arrival_s - now_s();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+      }
+      continue;
+    }
+    // one round of batched steps, then the stop flags of all active problems
+    ipm_status st = ipm_step(ctx, static_cast<int>(active_id.size()), active_id.data(),
+                             steps_per_round, nullptr);
+    if (st != IPM_OK) return st;
+    ctrl.resize(active_id.size());
+    for (size_t k = 0; k < active_id.size(); ++k)
+      HIPCHK(ctx, hipMemcpyAsync(&ctrl[k], get(ctx, active_id[k])->d_ctrl, sizeof(StepCtrl),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k < active_id.size();) {
+      const StepCtrl& hc = ctrl[k];
+      const bool done = hc.done[hc.steps & 1] || hc.status;
+      if (!done) {
+        ++k;
+        continue;
+      }
+      ipm_request& R = reqs[active_req[k]];
+      const int pid = active_id[k];
+      ipm_step_info info;
+      if ((st = enqueue_close(ctx, *get(ctx, pid))) != IPM_OK) return st;
+      if ((st = ipm_query(ctx, pid, &info)) != IPM_OK) return st;
+      R.status = info.status;
+      R.steps = info.steps;
+      if (R.moments_out && info.status == IPM_OK) {
+        st = ipm_moments(ctx, pid, R.moments_out, R.moments_len, 0);
+        if (st != IPM_OK) R.status = st;
+      }
+      if ((st = ipm_release(ctx, pid)) != IPM_OK) return st;
+      R.finished_s = now_s();
+      ++finished;
+      active_req.erase(active_req.begin() + static_cast<long>(k));
+      active_id.erase(active_id.begin() + static_cast<long>(k));
+      ctrl.erase(ctrl.begin() + static_cast<long>(k));
+    }
+  }
   return IPM_OK;
 }
 

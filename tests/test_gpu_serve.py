@@ -1,0 +1,91 @@
+"""GPU: the serving loop (ipm_serve).  Requests of different sizes and orders
+arrive over time, are admitted by slot and HBM footprint, run as one batch
+while they overlap, and leave when done.  Each result must equal the same
+problem stepped alone (bitwise: batching changes no arithmetic)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_09238_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    rng = np.random.default_rng(1912)
+    from paper_1912_09238_amd import binding
+    reqs, t = [], 0.0
+    for k in range(10):
+        t += 0.0005  # a burst: requests share rounds on the device
+        deg = int(rng.integers(3, 7))
+        if k % 5 < 3:
+            nx = int(rng.integers(64, 300))
+            spec = W.burgers_shock(nx=nx, degree=deg, qpd=2 * (deg + 1), t_end=0.004,
+                                   u_left=float(rng.uniform(8, 14)))
+            spec["u_plus"] = spec["ic"]["left"] + 0.2
+        else:
+            nx = int(rng.integers(100, 400))
+            spec = W.sod(nx=nx, degree=deg, qpd=2 * (deg + 1), t_end=0.01,
+                         spread=float(rng.uniform(0.02, 0.1)))
+        nodes, _ = binding.quadrature(1, spec["quad_per_dim"])
+        reqs.append({"spec": spec, "arrival": t, "ic_nodal": W.ic_nodal(spec, nodes)})
+    return reqs
+
+
+def _alone(ctx, rq):
+    pid = ctx.set_problem(rq["spec"], ic_nodal=rq["ic_nodal"])
+    while not ctx.step(pid, 64, wait=True)[0]["done"]:
+        pass
+    info = ctx.query(pid)
+    mom = ctx.moments(pid)
+    ctx.release(pid)
+    return info, mom
+
+
+def test_served_results_equal_alone(gpu_ctx):
+    reqs = _requests()
+    _say("gpu case: serve %d requests, rounds of 4 steps, 4 active" % len(reqs))
+    res = gpu_ctx.serve(reqs, steps_per_round=4, max_active=4)
+    overlap = 0
+    for k, (rq, r) in enumerate(zip(reqs, res)):
+        assert r["status"] == 0, (k, r)
+        assert r["admitted"] >= rq["arrival"] - 1e-9 and r["finished"] > r["admitted"]
+        info, mom = _alone(gpu_ctx, rq)
+        assert r["steps"] == info["steps"]
+        assert np.array_equal(r["moments"], mom), (k, np.max(np.abs(r["moments"] - mom)))
+        overlap = max(overlap, sum(1 for s in res if s["admitted"] < r["finished"] <= s["finished"]))
+    assert overlap >= 2  # requests really shared the device
+
+
+def test_admission_by_hbm_footprint():
+    from paper_1912_09238_amd import binding
+    import torch
+    torch.cuda.init()
+    reqs = _requests()
+    probe = binding.Context(device=0)
+    fps = [probe.footprint(rq["spec"]) for rq in reqs]
+    probe.close()
+    budget = int(1.5 * max(fps))
+    huge = W.sod(nx=200000, degree=9, qpd=20, t_end=1e-6)
+    nodes, _ = binding.quadrature(1, 20)
+    reqs.append({"spec": huge, "arrival": 0.0, "ic_nodal": W.ic_nodal(huge, nodes)})
+    _say("gpu case: serve with budget %d bytes" % budget)
+    ctx = binding.Context(device=0, hbm_budget=budget)
+    try:
+        res = ctx.serve(reqs, steps_per_round=4, max_active=16)
+    finally:
+        ctx.close()
+    assert res[-1]["status"] == -3  # cannot fit even alone
+    for k, r in enumerate(res[:-1]):
+        assert r["status"] == 0, (k, r)
+    # at every admission, the admitted requests' footprints fit the budget
+    for k, r in enumerate(res[:-1]):
+        t = r["admitted"]
+        live = [j for j, s in enumerate(res[:-1]) if s["admitted"] <= t < s["finished"]]
+        assert sum(fps[j] for j in live) <= budget, (k, live)
