@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -64,8 +66,143 @@ def cpu_baseline(spec, budget_s):
             "kbar": info["newton_iters"] / max(1, info["cell_updates"])}
 
 
+def _gpu_context(**kw):
+    import torch
+    from paper_1912_09238_amd import binding
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.init()
+    return binding.Context(device=0, stream=torch.cuda.current_stream().cuda_stream, **kw)
+
+
+def batch_form(args):
+    """Batching form: 64 uneven 2D Euler problems with three uncertainties,
+    per-cell total degree 1..4 (4..35 modes, 16..140 unknowns), 5^3 nodes,
+    stepped together (one launch per kernel shape, graph replay)."""
+    import torch
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    specs = W.batch_problems(count=args.batch_count)
+    nodes, _ = binding.quadrature(3, 5)
+    ids, cells, hist = [], 0, np.zeros(5, dtype=np.int64)
+    t_setup = time.perf_counter()
+    for k, spec in enumerate(specs):
+        cd = W.cell_degrees(spec)
+        hist += np.bincount(cd, minlength=5)
+        ids.append(ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes), cell_degree=cd))
+        cells += spec["nx"] * spec["ny"]
+        if k % 8 == 7:
+            print("batch set-up: %d problems, %d cells" % (k + 1, cells), file=sys.stderr, flush=True)
+    t_setup = time.perf_counter() - t_setup
+    tuned = ctx.autotune(ids, steps_per_candidate=1) if args.autotune else 0
+    ctx.step(ids, args.batch_warmup, wait=True)
+    before = ctx.step(ids, 0, wait=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(ids, args.batch_steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    after = ctx.step(ids, 0, wait=True)
+    assert all(a["status"] == 0 for a in after), after
+    done = sum((a["steps"] - b["steps"]) * (sp["nx"] * sp["ny"])
+               for a, b, sp in zip(after, before, specs))
+    newton = sum(a["newton_iters"] - b["newton_iters"] for a, b in zip(after, before))
+    value = done / elapsed
+    # the same problems stepped one at a time (per-problem launches), fewer steps
+    seq_steps = max(1, args.batch_steps // 10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for pid in ids:
+        ctx.step(pid, seq_steps)
+    torch.cuda.synchronize()
+    seq_value = cells * seq_steps / (time.perf_counter() - t1)
+    for pid in ids:
+        ctx.release(pid)
+    # many small problems: 64 Burgers shocks of 512 cells, degree 5 -- here the
+    # launch count, not the cell work, decides, and the batch shares launches
+    small = [W.burgers_shock(nx=512, degree=5, qpd=12, t_end=0.0) for _ in range(64)]
+    bn, _ = binding.quadrature(1, 12)
+    sids = [ctx.set_problem(sp, ic_nodal=W.ic_nodal(sp, bn)) for sp in small]
+    ctx.step(sids, 4, wait=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.step(sids, 200)
+    torch.cuda.synchronize()
+    small_batched = 64 * 512 * 200 / (time.perf_counter() - t2)
+    t3 = time.perf_counter()
+    for _ in range(20):
+        for pid in sids:
+            ctx.step(pid, 1)
+    torch.cuda.synchronize()
+    small_seq = 64 * 512 * 20 / (time.perf_counter() - t3)
+    for pid in sids:
+        ctx.release(pid)
+    ctx.close()
+    return {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.batch_steps, "warmup": args.batch_warmup,
+        "ms_per_step": elapsed / args.batch_steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch%d_euler2d_p3_deg1to4_q125_fp64" % len(specs),
+                   "problems": len(specs), "cells": cells,
+                   "cells_by_degree": {str(k): int(hist[k]) for k in range(1, 5)},
+                   "parallelism": "single-gpu"},
+        "one_problem_at_a_time": {"value": seq_value, "steps": seq_steps},
+        "small_problems_64x512_burgers_deg5": {"batched": small_batched,
+                                                "one_problem_at_a_time": small_seq},
+        "setup_s": t_setup, "autotuned_shapes": tuned,
+        "kbar": newton / max(1, done),
+    }
+
+
+def serve_form(args):
+    """Serving form: Poisson request stream (60 % Burgers, 40 % Sod, degree
+    3..9) through the library's serving loop; latency from arrival to moments
+    on the host."""
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context(hbm_budget=int(args.budget_gb * 2 ** 30))
+    reqs = []
+    for spec in W.request_stream(rate=args.rate, duration=args.duration):
+        nodes, _ = binding.quadrature(1, spec["quad_per_dim"])
+        reqs.append({"spec": spec, "arrival": spec["arrival"], "ic_nodal": W.ic_nodal(spec, nodes)})
+    t0 = time.perf_counter()
+    res = ctx.serve(reqs, steps_per_round=args.round, max_active=args.max_active, moments=False)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:3]
+    lat = np.array([r["latency"] for r in res])
+    work = sum(r["steps"] * rq["spec"]["nx"] for r, rq in zip(res, reqs))
+    makespan = max(r["finished"] for r in res)
+    return {
+        "metric": METRIC, "value": work / makespan, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serve_poisson%d_burgers60_sod40_fp64" % int(args.rate),
+                   "requests": len(reqs), "arrival_window_s": args.duration,
+                   "steps_per_round": args.round, "max_active": args.max_active,
+                   "hbm_budget_gb": args.budget_gb, "parallelism": "single-gpu"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "offered_cell_updates_per_s": work / args.duration,
+        "served_cell_updates_per_s": work / makespan, "makespan_s": makespan, "wall_s": wall,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+                    help="plain: the Sod throughput line (default); batch / serve: the "
+                         "batching and serving forms")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--duration", type=float, default=1.0)
+    ap.add_argument("--round", type=int, default=8)
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -80,6 +217,12 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.form == "batch":
+        print(json.dumps(batch_form(args)), flush=True)
+        return
+    if args.form == "serve":
+        print(json.dumps(serve_form(args)), flush=True)
+        return
 
     import torch
     from paper_1912_09238_amd import binding

@@ -39,11 +39,13 @@ namespace ipm {
 constexpr int kSlots = 64;
 constexpr int kSlotStride = 16;  // 128-byte spacing of atomic slots
 // Newton size classes of a cell with n unknowns: groups of 8, 16, 32, 64
-// lanes (n <= 64) or the workgroup-per-cell kernel (n > 64)
-constexpr int kCls = 5;
+// lanes (n <= 64), or the workgroup-per-cell kernel with 16 T x 16 T tiles,
+// T = 5, 6, 8, 9 (n <= 80, 96, 128, 144)
+constexpr int kCls = 8;
 __host__ __device__ inline int size_class(int n) {
-  return n > 64 ? 4 : n > 32 ? 3 : n > 16 ? 2 : n > 8 ? 1 : 0;
+  return n > 128 ? 7 : n > 96 ? 6 : n > 80 ? 5 : n > 64 ? 4 : n > 32 ? 3 : n > 16 ? 2 : n > 8 ? 1 : 0;
 }
+__host__ __device__ inline int class_tiles(int c) { return c == 4 ? 5 : c == 5 ? 6 : c == 6 ? 8 : 9; }
 
 struct StepCtrl {
   double t[2];                      // time by step parity
@@ -264,14 +266,33 @@ struct NewtonCfg {
 // the same for every lane, so they need not occupy LDS bandwidth.
 typedef const __attribute__((address_space(4))) double* const_dptr;
 
-// The cell of work item `item`: entry-major over the 64 lists of the launch's
-// size class, or the class's cells in ascending order.
+// The cell of work item `item`: the 64 lists of the launch's size class laid
+// end to end (a prefix sum over their lengths, so the listed cells occupy the
+// first items of the grid whatever their spread over the lists), or the
+// class's cells in ascending order.  Called by every thread of the block.
 __device__ __forceinline__ int work_cell(const DualParams& P, int item) {
   if (P.list_cap > 0) {
-    const int slot = item & (kSlots - 1), entry = item >> 6;
-    const int len = static_cast<int>(P.ctrl->list_len[list_len_index(P.parity, P.cls, slot)]);
-    return entry < min(len, P.list_cap) ? P.lists[static_cast<size_t>(slot) * P.list_cap + entry]
-                                        : -1;
+    __shared__ int pre[kSlots + 1];
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      int v = min(static_cast<int>(P.ctrl->list_len[list_len_index(P.parity, P.cls, lane)]),
+                  P.list_cap);
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+      }
+      pre[lane + 1] = v;
+      if (lane == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    if (item >= pre[kSlots]) return -1;
+    int lo = 0, hi = kSlots - 1;  // the list holding the item: last s with pre[s] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    return P.lists[static_cast<size_t>(lo) * P.list_cap + (item - pre[lo])];
   }
   if (P.order) return item < P.order_len ? P.order[item] : -1;
   return item < P.cells ? item : -1;
@@ -670,6 +691,31 @@ __device__ __forceinline__ int batch_problem(const int* __restrict__ begin, int 
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Block offsets of a batched list-mode Newton launch, from the lists the
+// flux update filled: problem k gets ceil(listed_k / per_block) blocks from
+// begin[k] on, so all listed cells sit in the first blocks of the grid.  It
+// also clears each problem's next-step lists and speed slots (the duty of
+// the problem's first Newton launch of the step, flagged reset_next).  One
+// wavefront.
+__global__ __launch_bounds__(64) void batch_prefix_kernel(const DualParams* __restrict__ PP, int n,
+                                                          int per_block, int* __restrict__ begin) {
+  const int lane = threadIdx.x;
+  int acc = 0;
+  if (lane == 0) begin[0] = 0;
+  for (int k = 0; k < n; ++k) {
+    const DualParams& P = PP[k];
+    int listed = 0;
+    if (!(P.ctrl->done[P.parity] || P.ctrl->status)) {
+      const int v = min(static_cast<int>(P.ctrl->list_len[list_len_index(P.parity, P.cls, lane)]),
+                        P.list_cap);
+      listed = static_cast<int>(wave_sum(static_cast<double>(v)));
+      if (P.reset_next) reset_next_step(P);
+    }
+    acc += (listed + per_block - 1) / per_block;
+    if (lane == 0) begin[k + 1] = acc;
+  }
 }
 
 template <int M, int NP>

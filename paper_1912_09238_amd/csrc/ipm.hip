@@ -77,6 +77,8 @@ struct Problem {
 // a single problem's steady-residual kernel.
 struct BatchLaunch {
   int kind = 0;  // 0: Newton (batched), 1: update (batched), 2: residual
+  bool lists = false;  // Newton over the step's lists: block offsets computed on the device
+  int per_block = 1;   // cells per Newton block
   const void* fn = nullptr;
   int blocks = 0, threads = 0;
   size_t lds = 0;
@@ -98,6 +100,7 @@ struct BatchPlan {
   DualParams* d_dp = nullptr;    // [2][nd]
   UpdateParams* d_up = nullptr;  // [2][nu]
   int* d_begin = nullptr;
+  int* d_dev_begin = nullptr;  // device-computed block offsets of list-mode Newton launches
   size_t nd = 0, nu = 0;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -109,6 +112,7 @@ struct BatchPlan {
     if (d_dp) (void)hipFree(d_dp);
     if (d_up) (void)hipFree(d_up);
     if (d_begin) (void)hipFree(d_begin);
+    if (d_dev_begin) (void)hipFree(d_dev_begin);
   }
 };
 
@@ -326,7 +330,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   for (int c = 0; c < kCls; ++c) {
     DualClass& D = P.cls[c];
     if (!D.configured) continue;
-    if (c == 4) {
+    if (c >= 4) {
       // workgroup per cell; the tile layout needs m | 16 (m = 1 or 4)
       if (16 % P.M != 0)
         return fail(ctx, IPM_E_ARG,
@@ -334,7 +338,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
                     "and m = 4 only");
       if (n > 144)
         return fail(ctx, IPM_E_ARG, "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
-      D.T = n <= 80 ? 5 : n <= 96 ? 6 : n <= 128 ? 8 : 9;
+      D.T = class_tiles(c);
       D.NP = 16 * D.T;
     } else {
       D.NP = 8 << c;
@@ -660,7 +664,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         const std::string key = std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                 std::to_string(D.T) + ":" + std::to_string(threads);
         ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
-        nshape[key] = {threads, P.M};
+        nshape[key] = {threads, per_block};
         nfn[key] = pick_newton_batched(P.M, D.NP, D.T);
         if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
       }
@@ -680,6 +684,8 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
       L.kind = 0;
       L.fn = nfn[kv.first];
       L.threads = nshape[kv.first].first;
+      L.per_block = nshape[kv.first].second;
+      L.lists = kv.second.front().d.list_cap > 0 || kv.second.front().d.lists != nullptr;
       L.pofs = dps.size();
       L.bofs = static_cast<int>(begins.size());
       L.n = static_cast<int>(kv.second.size());
@@ -727,6 +733,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
                              hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(B->d_begin, begins.data(), begins.size() * sizeof(int),
                              hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMalloc(&B->d_dev_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   // one graph per parity: Newton launches in parallel, then the updates,
   // then the steady residuals
@@ -743,13 +750,29 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
       if (L.kind == 0 || L.kind == 1) {
         const void* pp = L.kind == 0 ? static_cast<const void*>(B->d_dp + L.pofs)
                                      : static_cast<const void*>(B->d_up + L.pofs);
-        const int* bg = B->d_begin + L.bofs;
+        const int* bg = (L.kind == 0 && L.lists) ? B->d_dev_begin + L.bofs : B->d_begin + L.bofs;
         int n = L.n;
+        std::vector<hipGraphNode_t> deps;
+        if (L.kind == 1) deps = newton;
+        if (L.kind == 0 && L.lists) {
+          hipKernelNodeParams pk{};
+          const DualParams* pdp = B->d_dp + L.pofs;
+          int per_block = L.per_block;
+          int* out = B->d_dev_begin + L.bofs;
+          void* pargs[4] = {&pdp, &n, &per_block, &out};
+          pk.func = reinterpret_cast<void*>(batch_prefix_kernel);
+          pk.gridDim = dim3(1);
+          pk.blockDim = dim3(64);
+          pk.sharedMemBytes = 0;
+          pk.kernelParams = pargs;
+          pk.extra = nullptr;
+          hipGraphNode_t pnode;
+          HIPCHK(ctx, hipGraphAddKernelNode(&pnode, B->graph[ph], nullptr, 0, &pk));
+          deps.push_back(pnode);
+        }
         void* args[3] = {&pp, &bg, &n};
         kp.func = const_cast<void*>(L.fn);
         kp.kernelParams = args;
-        const std::vector<hipGraphNode_t> none;
-        const std::vector<hipGraphNode_t>& deps = L.kind == 0 ? none : newton;
         HIPCHK(ctx, hipGraphAddKernelNode(&node, B->graph[ph], deps.data(), deps.size(), &kp));
         (L.kind == 0 ? newton : update).push_back(node);
       } else {
@@ -811,8 +834,13 @@ ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
         if (L.kind == 0 || L.kind == 1) {
           const void* pp = L.kind == 0 ? static_cast<const void*>(B.d_dp + L.pofs)
                                        : static_cast<const void*>(B.d_up + L.pofs);
-          const int* bg = B.d_begin + L.bofs;
+          const int* bg = (L.kind == 0 && L.lists) ? B.d_dev_begin + L.bofs : B.d_begin + L.bofs;
           int n = L.n;
+          if (L.kind == 0 && L.lists) {
+            hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(64), 0, ctx->stream,
+                               B.d_dp + L.pofs, n, L.per_block, B.d_dev_begin + L.bofs);
+            HIPCHK(ctx, hipGetLastError());
+          }
           void* args[3] = {&pp, &bg, &n};
           HIPCHK(ctx, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.threads), args, L.lds, ctx->stream));
         } else {
@@ -1034,7 +1062,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
   std::vector<int8_t> cellN;
-  int counts[kCls] = {0, 0, 0, 0, 0};
+  int counts[kCls] = {};
   std::vector<int> cell_cls;
   if (pb->cell_degree) {
     cellN.resize(P.cells);
