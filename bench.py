@@ -155,6 +155,57 @@ def batch_form(args):
     }
 
 
+def precision_form(args):
+    """Precision form: 2D Euler bump on a periodic 512 x 512 grid, two
+    uncertainties, total degree 5 (21 modes, 84 unknowns per cell), 8 x 8
+    nodes: the same steps in the FP64 form and with the split-BF16 MFMA
+    Hessian, and the relative L1 difference of E and Var between them."""
+    import torch
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    spec = W.bump2d(n=args.prec_n, degree=5, qpd=8)
+    nodes, _ = binding.quadrature(2, 8)
+    ic = W.ic_nodal(spec, nodes)
+    cells = spec["nx"] * spec["ny"]
+    out = {}
+    for prec in ("fp64", "bf16"):
+        pid = ctx.set_problem(dict(spec, precision=prec), ic_nodal=ic)
+        ctx.step(pid, args.prec_warmup, wait=True)
+        b = ctx.step(pid, 0, wait=True)[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(pid, args.prec_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        a = ctx.step(pid, 0, wait=True)[0]
+        assert a["status"] == 0, a
+        out[prec] = {"value": cells * args.prec_steps / el, "ms_per_step": el / args.prec_steps * 1e3,
+                     "kbar": (a["newton_iters"] - b["newton_iters"]) / (cells * args.prec_steps),
+                     "moments": ctx.moments(pid)}
+        ctx.release(pid)
+        print("precision form: %s %.4g cell-updates/s" % (prec, out[prec]["value"]),
+              file=sys.stderr, flush=True)
+    ctx.close()
+    m64, m16 = out["fp64"]["moments"], out["bf16"]["moments"]
+    E64, E16 = m64[:, :, 0], m16[:, :, 0]
+    V64, V16 = np.sum(m64[:, :, 1:] ** 2, axis=2), np.sum(m16[:, :, 1:] ** 2, axis=2)
+    rel = lambda a, b: float(np.abs(a - b).sum() / np.abs(b).sum())
+    return {
+        "metric": METRIC, "value": out["bf16"]["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.prec_steps, "warmup": args.prec_warmup,
+        "ms_per_step": out["bf16"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16-mfma-hessian/f64", "data": "synthetic",
+        "config": {"workload": "euler2d_bump_%dx%d_deg5_q64" % (args.prec_n, args.prec_n),
+                   "cells": cells, "n": 84, "Q": 64, "parallelism": "single-gpu"},
+        "fp64_form": {"value": out["fp64"]["value"], "ms_per_step": out["fp64"]["ms_per_step"],
+                      "kbar": out["fp64"]["kbar"]},
+        "bf16_kbar": out["bf16"]["kbar"],
+        "speedup_vs_fp64": out["bf16"]["value"] / out["fp64"]["value"],
+        "rel_l1_vs_fp64": {"E": rel(E16, E64), "Var": rel(V16, V64)},
+    }
+
+
 def serve_form(args):
     """Serving form: Poisson request stream (60 % Burgers, 40 % Sod, degree
     3..9) through the library's serving loop; latency from arrival to moments
@@ -191,7 +242,7 @@ def serve_form(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision"], default="plain",
                     help="plain: the Sod throughput line (default); batch / serve: the "
                          "batching and serving forms")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -203,6 +254,9 @@ def main():
     ap.add_argument("--round", type=int, default=8)
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--prec-n", type=int, default=512)
+    ap.add_argument("--prec-steps", type=int, default=20)
+    ap.add_argument("--prec-warmup", type=int, default=2)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -222,6 +276,9 @@ def main():
         return
     if args.form == "serve":
         print(json.dumps(serve_form(args)), flush=True)
+        return
+    if args.form == "precision":
+        print(json.dumps(precision_form(args)), flush=True)
         return
 
     import torch

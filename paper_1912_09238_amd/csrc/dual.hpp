@@ -92,6 +92,7 @@ struct DualParams {
   int reset_next;                   // block 0 clears the next step's lists and speed slots
   const int* __restrict__ order;    // [order_len] cells of this class, ascending
   int order_len;
+  int bcache;                       // precision form: B fragments cached in LDS
 };
 
 // ---------------------------------------------------------------- helpers

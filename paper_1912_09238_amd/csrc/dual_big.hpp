@@ -12,6 +12,13 @@
 //     rows of a tile share the variable a = tr mod M and all columns the
 //     variable b = tc mod M, so a tile's entries take one entry J_ab of the
 //     closure Jacobian per node and the sum over nodes is a rank-1 update;
+//   - precision form (PREC = 1): each unique block H_ab = Phi^T diag(w J_ab)
+//     Phi (symmetric in the mode indices, H_ab = H_ba) is a matrix product
+//     on the MFMA units, v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
+//     both operands are split into BF16 high and low parts and three
+//     products are summed (about 16 significant bits).  The blocks land in
+//     LDS and every thread gathers its FP64 tile.  Gradient, tau test and the
+//     solve stay FP64, so the Newton loop still stops at the FP64 tolerance;
 //   - Gauss-Jordan without pivoting (H is SPD): the owners of the pivot
 //     column publish it to LDS, one barrier per step; every thread reads the
 //     column entries of its rows (multipliers) and, by symmetry of the
@@ -24,18 +31,35 @@
 
 namespace ipm {
 
-template <int M, int T>
+template <int M, int T, int PREC = 0>
 struct BigCfg {
   static_assert(16 % M == 0, "tile variables need M | 16");
   static constexpr int NPB = 16 * T;  // unknowns incl. identity padding
   static constexpr int NJ = M * (M + 1) / 2;
-  __host__ __device__ static size_t lds_bytes(int Q, int kp) {
+  __host__ __device__ static size_t lds_bytes(int Q, int kp, bool bcache = true) {
     // phi [Q][kp]; w [Q]; lam [NPB]; U [Q][M]; J [Q][NJ]; column [2][NPB];
     // pivot-row rhs [2]; reduction scratch [4][8]
-    return sizeof(double) * (static_cast<size_t>(Q) * kp + Q + NPB +
-                             static_cast<size_t>(Q) * (M + NJ) + 2 * NPB + 2 + 32);
+    size_t b = sizeof(double) * (static_cast<size_t>(Q) * kp + Q + NPB +
+                                 static_cast<size_t>(Q) * (M + NJ) + 2 * NPB + 2 + 32);
+    if (PREC == 1) {
+      // FP32 blocks [NJ][16 NT][16 NT] and BF16 hi/lo B fragments
+      // [NT][QC][64 lanes][16], NT = ceil(N / 16), QC = ceil(Q / 32), N <= kp
+      const size_t nt = (kp + 15) / 16, qc = (Q + 31) / 32;
+      b += sizeof(float) * NJ * (16 * nt) * (16 * nt) + (bcache ? 32 * 64 * nt * qc : 0);
+    }
+    return b;
   }
 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo with hi, lo in BF16 (round to nearest): hi carries 8
+// significant bits, hi + lo about 16
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = static_cast<__bf16>(x);
+  lo = static_cast<__bf16>(x - static_cast<float>(hi));
+}
 
 // Sum over the workgroup (256 threads, all active) of K values per thread.
 // Fixed reduction order: identical results in every thread and every run.
@@ -54,9 +78,9 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   __syncthreads();
 }
 
-template <int M, int T>
+template <int M, int T, int PREC>
 __device__ __forceinline__ void newton_big_body(const DualParams& P, const int blk) {
-  using Cfg = BigCfg<M, T>;
+  using Cfg = BigCfg<M, T, PREC>;
   constexpr int NPB = Cfg::NPB, NJ = Cfg::NJ;
   if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
@@ -76,6 +100,35 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   double* red = xk + 2;            // [32]
   for (int k = tid; k < Q * kp; k += 256) phiL[k] = P.phi[k];
   for (int q = tid; q < Q; q += 256) wL[q] = P.wphi[static_cast<size_t>(q) * kp];
+  // precision form: FP32 Hessian blocks and the constant B fragments phi_k(q)
+  const int NT = (kp + 15) / 16, QC = (Q + 31) / 32, S16 = 16 * NT;
+  float* Hb = reinterpret_cast<float*>(red + 32);                        // [NJ][S16][S16]
+  bf16x8* Bf = reinterpret_cast<bf16x8*>(Hb + static_cast<size_t>(NJ) * S16 * S16);  // [NT][QC][2][64]
+  // B fragment f = K QC + c of this lane: phi_k(q) for its column k and 8 nodes
+  auto b_fragment = [&](int f, bf16x8& hi, bf16x8& lo) {
+    const int K = f / QC, c = f % QC, lane = tid & 63;
+    const int k = K * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = c * 32 + 8 * (lane >> 4) + j;
+      const float v = (q < Q && k < N) ? static_cast<float>(phiL[q * kp + k]) : 0.0f;
+      __bf16 h, l;
+      split_bf16(v, h, l);
+      hi[j] = h;
+      lo[j] = l;
+    }
+  };
+  if constexpr (PREC == 1) {
+    __syncthreads();  // phiL is complete
+    if (P.bcache)
+      for (int f = tid >> 6; f < NT * QC; f += 4) {
+        const int lane = tid & 63;
+        bf16x8 hi, lo;
+        b_fragment(f, hi, lo);
+        Bf[(static_cast<size_t>(f) * 2) * 64 + lane] = hi;
+        Bf[(static_cast<size_t>(f) * 2 + 1) * 64 + lane] = lo;
+      }
+  }
 
   const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
   const int nc = Nc * M;
@@ -134,45 +187,108 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     }
     // ---- Hessian tiles
     double H[T][T];
+    if constexpr (PREC == 1) {
+      // blocks H_ab[i][k] = sum_q w_q J_ab(q) phi_i(q) phi_k(q) on the MFMA
+      // units: task (ab, I) builds the A fragments of row tile I once per
+      // chunk of 32 nodes and runs all column tiles K
+      const int lane = tid & 63, NTc = (Nc + 15) / 16;
+      for (int task = tid >> 6; task < NJ * NTc; task += 4) {
+        const int ab = task / NTc, I = task % NTc;
+        const int i = I * 16 + (lane & 15);
+        constexpr int KT = (T + M - 1) / M;  // column tiles of the largest N of the class
+        f32x4 acc[KT];
 #pragma unroll
-    for (int i = 0; i < T; ++i)
+        for (int K = 0; K < KT; ++K) acc[K] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < QC; ++c) {
+          bf16x8 ahi, alo;
 #pragma unroll
-      for (int j = 0; j < T; ++j) H[i][j] = 0.0;
-    {
-      int li[T], lj[T];
-      double mi[T], mj[T];
+          for (int j = 0; j < 8; ++j) {
+            const int q = c * 32 + 8 * (lane >> 4) + j;
+            const float v = (q < Q && i < Nc)
+                                ? static_cast<float>(wL[q] * JS[q * NJ + ab] * phiL[q * kp + i])
+                                : 0.0f;
+            __bf16 h, l;
+            split_bf16(v, h, l);
+            ahi[j] = h;
+            alo[j] = l;
+          }
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const int r = tr + 16 * i;
-        li[i] = r < nc ? r / M : 0;
-        mi[i] = r < nc ? 1.0 : 0.0;
+          for (int K = 0; K < KT; ++K) {
+            if (K < NTc) {
+              const size_t f = static_cast<size_t>(K) * QC + c;
+              bf16x8 bhi, blo;
+              if (P.bcache) {
+                bhi = Bf[(f * 2) * 64 + lane];
+                blo = Bf[(f * 2 + 1) * 64 + lane];
+              } else {
+                b_fragment(static_cast<int>(f), bhi, blo);
+              }
+              acc[K] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[K], 0, 0, 0);
+              acc[K] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[K], 0, 0, 0);
+              acc[K] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[K], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int K = 0; K < KT; ++K)
+          if (K < NTc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              Hb[(static_cast<size_t>(ab) * S16 + I * 16 + 4 * (lane >> 4) + r) * S16 + K * 16 +
+                 (lane & 15)] = acc[K][r];
       }
-#pragma unroll
-      for (int j = 0; j < T; ++j) {
-        const int c = tc + 16 * j;
-        lj[j] = c < nc ? c / M : 0;
-        mj[j] = c < nc ? 1.0 : 0.0;
-      }
-      for (int q = 0; q < Q; ++q) {
-        const double s = JS[q * NJ + jidx] * wL[q];
-        double lv[T], rv[T];
-#pragma unroll
-        for (int i = 0; i < T; ++i) lv[i] = phiL[q * kp + li[i]] * (s * mi[i]);
-#pragma unroll
-        for (int j = 0; j < T; ++j) rv[j] = phiL[q * kp + lj[j]] * mj[j];
-#pragma unroll
-        for (int i = 0; i < T; ++i)
-#pragma unroll
-          for (int j = 0; j < T; ++j) H[i][j] = fma(lv[i], rv[j], H[i][j]);
-      }
-      // identity beyond the cell's unknowns
+      __syncthreads();
+      const int ab = Packed<M>::idx(tr % M, tc % M);
 #pragma unroll
       for (int i = 0; i < T; ++i)
 #pragma unroll
         for (int j = 0; j < T; ++j) {
           const int r = tr + 16 * i, c = tc + 16 * j;
-          if (r >= nc || c >= nc) H[i][j] = (r == c) ? 1.0 : 0.0;
+          H[i][j] = (r < nc && c < nc)
+                        ? static_cast<double>(Hb[(static_cast<size_t>(ab) * S16 + r / M) * S16 + c / M])
+                        : (r == c ? 1.0 : 0.0);
         }
+    } else {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) H[i][j] = 0.0;
+      {
+        int li[T], lj[T];
+        double mi[T], mj[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+          const int r = tr + 16 * i;
+          li[i] = r < nc ? r / M : 0;
+          mi[i] = r < nc ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int c = tc + 16 * j;
+          lj[j] = c < nc ? c / M : 0;
+          mj[j] = c < nc ? 1.0 : 0.0;
+        }
+        for (int q = 0; q < Q; ++q) {
+          const double s = JS[q * NJ + jidx] * wL[q];
+          double lv[T], rv[T];
+#pragma unroll
+          for (int i = 0; i < T; ++i) lv[i] = phiL[q * kp + li[i]] * (s * mi[i]);
+#pragma unroll
+          for (int j = 0; j < T; ++j) rv[j] = phiL[q * kp + lj[j]] * mj[j];
+#pragma unroll
+          for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j) H[i][j] = fma(lv[i], rv[j], H[i][j]);
+        }
+        // identity beyond the cell's unknowns
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            const int r = tr + 16 * i, c = tc + 16 * j;
+            if (r >= nc || c >= nc) H[i][j] = (r == c) ? 1.0 : 0.0;
+          }
+      }
     }
     // ---- Gauss-Jordan solve H d = g
     double x = g, dg = 1.0;
@@ -306,16 +422,21 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   }
 }
 
-template <int M, int T>
-__global__ __launch_bounds__(256) void newton_big_kernel(DualParams P) {
-  newton_big_body<M, T>(P, blockIdx.x);
+// two workgroups per CU for the precision form up to T = 6 (its per-cell
+// latency is the lower one, so the launch is occupancy bound); larger tiles
+// do not fit two wavefronts' registers
+template <int M, int T, int PREC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 1 && T <= 6) ? 2 : 1)))
+void newton_big_kernel(DualParams P) {
+  newton_big_body<M, T, PREC>(P, blockIdx.x);
 }
 
-template <int M, int T>
-__global__ __launch_bounds__(256) void newton_big_batched(const DualParams* __restrict__ PP,
+template <int M, int T, int PREC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 1 && T <= 6) ? 2 : 1)))
+void newton_big_batched(const DualParams* __restrict__ PP,
                                                           const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
-  newton_big_body<M, T>(PP[k], blockIdx.x - begin[k]);
+  newton_big_body<M, T, PREC>(PP[k], blockIdx.x - begin[k]);
 }
 
 }  // namespace ipm

@@ -33,6 +33,8 @@ thread_local std::string g_create_error;
 // Newton launch configuration of one size class of a problem's cells
 struct DualClass {
   bool configured = false;  // kernel chosen (cells of the class, or the ghosts' full size)
+  int prec = 0;             // 1: BF16-split MFMA Hessian (precision form, workgroup kernel)
+  int bcache = 1;           // precision form: B fragments cached in LDS (when they fit)
   int NP = 8;               // lanes per cell (small kernel) or 16 T (workgroup kernel)
   int T = 0;                // > 0: workgroup kernel with T x T tiles
   int waves = 4;            // small kernel: wavefronts per block
@@ -190,15 +192,37 @@ DualFn big_fn(int T) {
   return nullptr;
 }
 
-DualFn pick_big(int M, int T) {
+template <int M>
+DualFn big_fn_prec(int T) {
+  switch (T) {
+    case 5: return newton_big_kernel<M, 5, 1>;
+    case 6: return newton_big_kernel<M, 6, 1>;
+    case 8: return newton_big_kernel<M, 8, 1>;
+    case 9: return newton_big_kernel<M, 9, 1>;
+  }
+  return nullptr;
+}
+
+DualFn pick_big(int M, int T, int prec = 0) {
+  if (prec == 1) {
+    if (M == 1) return big_fn_prec<1>(T);
+    if (M == 4) return big_fn_prec<4>(T);
+    return nullptr;
+  }
   if (M == 1) return big_fn<1>(T);
   if (M == 4) return big_fn<4>(T);
   return nullptr;
 }
 
-size_t big_lds_bytes(int M, int T, int Q, int kp) {
+size_t big_lds_bytes(int M, int T, int Q, int kp, int prec = 0, bool bcache = true) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
+    if (prec == 1) switch (T) {
+        case 5: return BigCfg<MM, 5, 1>::lds_bytes(Q, kp, bcache);
+        case 6: return BigCfg<MM, 6, 1>::lds_bytes(Q, kp, bcache);
+        case 8: return BigCfg<MM, 8, 1>::lds_bytes(Q, kp, bcache);
+        default: return BigCfg<MM, 9, 1>::lds_bytes(Q, kp, bcache);
+      }
     switch (T) {
       case 1: return BigCfg<MM, 1>::lds_bytes(Q, kp);
       case 2: return BigCfg<MM, 2>::lds_bytes(Q, kp);
@@ -340,6 +364,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
         return fail(ctx, IPM_E_ARG, "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
       D.T = class_tiles(c);
       D.NP = 16 * D.T;
+      D.prec = P.precision == IPM_PREC_BF16 ? 1 : 0;
     } else {
       D.NP = 8 << c;
       P.kp = std::max(P.kp, dual_table_columns(P.M, D.NP));
@@ -372,7 +397,12 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     }
     if (D.T > 0) {
       D.waves = 4;
-      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp);
+      D.bcache = 1;
+      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true);
+      if (D.prec == 1 && D.lds > ctx->max_lds) {  // build the B fragments on the fly instead
+        D.bcache = 0;
+        D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false);
+      }
     }
     if (D.lds > ctx->max_lds)
       return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
@@ -424,6 +454,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
                        int ghost_cells = -1) {
   const DualClass& D = P.cls[c];
   d.cls = c;
+  d.bcache = D.bcache;
   int items;
   if (ghost_cells >= 0) {
     d.list_cap = 0;
@@ -444,7 +475,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
   }
   if (items == 0) return IPM_OK;
   if (D.T > 0) {
-    DualFn fn = pick_big(P.M, D.T);
+    DualFn fn = pick_big(P.M, D.T, D.prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     hipLaunchKernelGGL(fn, dim3(items), dim3(256), D.lds, ctx->stream, d);
   } else {
@@ -558,9 +589,15 @@ ipm_status enqueue_close(ipm_ctx* ctx, Problem& P) {
 // ---------------------------------------------------------------- batching
 
 template <int M>
-const void* newton_batched_fn(int NP, int T) {
+const void* newton_batched_fn(int NP, int T, int prec) {
   if (T > 0) {
     if constexpr (16 % M == 0) {
+      if (prec == 1) switch (T) {
+          case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5, 1>);
+          case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6, 1>);
+          case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8, 1>);
+          case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9, 1>);
+        }
       switch (T) {
         case 1: return reinterpret_cast<const void*>(newton_big_batched<M, 1>);
         case 2: return reinterpret_cast<const void*>(newton_big_batched<M, 2>);
@@ -582,10 +619,10 @@ const void* newton_batched_fn(int NP, int T) {
   return nullptr;
 }
 
-const void* pick_newton_batched(int M, int NP, int T) {
-  if (M == 1) return newton_batched_fn<1>(NP, T);
-  if (M == 3) return newton_batched_fn<3>(NP, T);
-  if (M == 4) return newton_batched_fn<4>(NP, T);
+const void* pick_newton_batched(int M, int NP, int T, int prec = 0) {
+  if (M == 1) return newton_batched_fn<1>(NP, T, prec);
+  if (M == 3) return newton_batched_fn<3>(NP, T, prec);
+  if (M == 4) return newton_batched_fn<4>(NP, T, prec);
   return nullptr;
 }
 
@@ -645,6 +682,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         if (D.count == 0) continue;
         DualParams dc = d;
         dc.cls = c;
+        dc.bcache = D.bcache;
         dc.reset_next = first ? 1 : 0;
         first = false;
         dc.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
@@ -662,10 +700,11 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
         const std::string key = std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
-                                std::to_string(D.T) + ":" + std::to_string(threads);
+                                std::to_string(D.T) + ":" + std::to_string(threads) + ":" +
+                                std::to_string(D.prec);
         ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
         nshape[key] = {threads, per_block};
-        nfn[key] = pick_newton_batched(P.M, D.NP, D.T);
+        nfn[key] = pick_newton_batched(P.M, D.NP, D.T, D.prec);
         if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
       }
       const std::string ukey = std::to_string(P.M) + ":" + std::to_string(P.UG);
@@ -872,12 +911,14 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
   for (int M : {1, 4})
-    for (int T : {1, 2, 4, 5, 6, 8, 9}) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T)),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
-      (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    }
+    for (int T : {1, 2, 4, 5, 6, 8, 9})
+      for (int prec : {0, 1}) {
+        if (prec == 1 && T < 5) continue;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T, prec)),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T, prec),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      }
   for (int M : {1, 3, 4}) {
     for (int NP : {8, 16, 32, 64})
       (void)hipFuncSetAttribute(pick_newton_batched(M, NP, 0),
@@ -907,8 +948,10 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
   if (pb->quad_per_dim < 1 || pb->quad_per_dim > 64)
     return fail(ctx, IPM_E_ARG, "quad_per_dim must be 1..64");
   if (pb->precision < 0 || pb->precision > 2) return fail(ctx, IPM_E_ARG, "precision out of range");
-  if (pb->precision != IPM_PREC_FP64)
-    return fail(ctx, IPM_E_ARG, "reduced-precision Hessian assembly needs the MFMA path (m*N > 64)");
+  if (pb->precision == IPM_PREC_FP32)
+    return fail(ctx, IPM_E_ARG,
+                "IPM_PREC_FP32 is not provided: on this GPU FP32 vector arithmetic runs at the FP64 "
+                "rate; use IPM_PREC_BF16 (split-BF16 MFMA Hessian)");
   if (!(pb->cfl > 0.0)) return fail(ctx, IPM_E_ARG, "cfl must be > 0");
   if (!(pb->tau > 0.0)) return fail(ctx, IPM_E_ARG, "tau must be > 0");
   if (pb->t_end < 0.0 || pb->steady_eps < 0.0)
