@@ -122,6 +122,21 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_bit_cast(double, x);
 }
 
+// acc += (lane N of this 16-lane row's src) * mul, one instruction: the
+// row_newbcast DPP operand of v_fmac_f64.  Pure ALU; the caller separates it
+// from the VALU write of src by at least two wait states (see dpp_guard).
+template <int N>
+__device__ __forceinline__ void fmac_row_bcast(double& acc, double src, double mul) {
+  asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+               : "+v"(acc)
+               : "v"(src), "v"(mul), "i"(N));
+}
+// Two wait states between the VALU writes of a and b and the DPP reads that
+// follow: a and b are inputs, so their producers are scheduled before it.
+__device__ __forceinline__ void dpp_guard(double a, double b) {
+  asm volatile("s_nop 1" : : "v"(a), "v"(b));
+}
+
 // For aligned 32-lane groups: lo holds the group's lanes 0..15 in both of its
 // 16-lane rows, hi its lanes 16..31 (v_permlane16_swap on each 32-bit half).
 __device__ __forceinline__ void group32_halves(double v, double& lo, double& hi) {
@@ -488,11 +503,13 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
             pd_ok &= piv > 0.0 ? 1 : 0;
             if (r == k) dg = piv;
             const double f = (r == k) ? 0.0 : row[0][k] * recip(piv);
+            const double negf = -f;
             xv = fma(-f, gk, xv);
+            dpp_guard(clo, chi);
             static_for<k + 1, NP>([&](auto jc) __attribute__((always_inline)) {
               constexpr int j = decltype(jc)::value;
-              const double aj = (j < 16) ? row_bcast<j % 16>(clo) : row_bcast<j % 16>(chi);
-              row[0][j] = fma(-f, aj, row[0][j]);
+              if constexpr (j == 16 && k + 1 < 16) dpp_guard(clo, chi);
+              fmac_row_bcast<j % 16>(row[0][j], (j < 16) ? clo : chi, negf);
             });
           }
           // one step at a time: interleaving steps keeps every step's
