@@ -114,6 +114,34 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
 
   __shared__ double sh_speed[2];
   __shared__ int s_route[16];
+  const int lane = threadIdx.x & 63;
+  const int gid = (threadIdx.x >> 6) * CPW + lane / G;
+  const int r = lane % G;
+  const int cell = blk * groups + gid;
+  // operands that do not depend on the time step are requested before the
+  // step's speed reduction, so the two memory round trips overlap: this
+  // lane's first node of the cell and of its neighbours, its first old moment
+  const double *uc = nullptr, *uw = nullptr, *ue = nullptr, *us = nullptr, *un = nullptr;
+  double pc[M], pw[M], pe[M], ps[M], pn[M], uold0 = 0.0;
+  if (cell < P.cells) {
+    const int ix = cell % P.nx, iy = cell / P.nx;
+    uc = P.nodal + static_cast<size_t>(cell) * Q * M;
+    uw = neighbour_nodal<M>(P, ix, iy, 0);
+    ue = neighbour_nodal<M>(P, ix, iy, 1);
+    us = P.dim == 2 ? neighbour_nodal<M>(P, ix, iy, 2) : uc;
+    un = P.dim == 2 ? neighbour_nodal<M>(P, ix, iy, 3) : uc;
+    if (r < Q) {
+#pragma unroll
+      for (int b = 0; b < M; ++b) {
+        pc[b] = uc[r * M + b];
+        pw[b] = uw[r * M + b];
+        pe[b] = ue[r * M + b];
+        ps[b] = us[r * M + b];
+        pn[b] = un[r * M + b];
+      }
+    }
+    if (r < M * N) uold0 = P.uold[static_cast<size_t>(cell) * M * N + r];
+  }
   double ax, ay;
   step_speeds(C, P.parity, P.dim, ax, ay, sh_speed);
   const double t0 = C->t[P.parity];
@@ -125,29 +153,20 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
   }
   const double lfx = P.dx / (2.0 * dt), lfy = P.dy / (2.0 * dt);
 
-  const int lane = threadIdx.x & 63;
-  const int gid = (threadIdx.x >> 6) * CPW + lane / G;
-  const int r = lane % G;
-  const int cell = blk * groups + gid;
   double* ut = UT + static_cast<size_t>(gid) * Q * M;
   double* uq = UC + static_cast<size_t>(gid) * Q * M;
   double res_cell = 0.0, nx_speed = 0.0, ny_speed = 0.0;
   int finite = 1, route = 0;
   if (cell < P.cells) {
-    const int ix = cell % P.nx, iy = cell / P.nx;
-    const double* uc = P.nodal + static_cast<size_t>(cell) * Q * M;
-    const double* uw = neighbour_nodal<M>(P, ix, iy, 0);
-    const double* ue = neighbour_nodal<M>(P, ix, iy, 1);
-    const double* us = P.dim == 2 ? neighbour_nodal<M>(P, ix, iy, 2) : uc;
-    const double* un = P.dim == 2 ? neighbour_nodal<M>(P, ix, iy, 3) : uc;
     const double rx = dt / P.dx, ry = dt / P.dy;
     for (int q = r; q < Q; q += G) {
       double c[M], l[M], rr[M], gl[M], gr[M], acc[M];
+      const bool first = q == r;
 #pragma unroll
       for (int b = 0; b < M; ++b) {
-        c[b] = uc[q * M + b];
-        l[b] = uw[q * M + b];
-        rr[b] = ue[q * M + b];
+        c[b] = first ? pc[b] : uc[q * M + b];
+        l[b] = first ? pw[b] : uw[q * M + b];
+        rr[b] = first ? pe[b] : ue[q * M + b];
       }
       numerical_flux<M>(P.flux, P.gamma, 0, c, rr, lfx, gr);
       numerical_flux<M>(P.flux, P.gamma, 0, l, c, lfx, gl);
@@ -156,8 +175,8 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
       if (P.dim == 2) {
 #pragma unroll
         for (int b = 0; b < M; ++b) {
-          l[b] = us[q * M + b];
-          rr[b] = un[q * M + b];
+          l[b] = first ? ps[b] : us[q * M + b];
+          rr[b] = first ? pn[b] : un[q * M + b];
         }
         numerical_flux<M>(P.flux, P.gamma, 1, c, rr, lfy, gr);
         numerical_flux<M>(P.flux, P.gamma, 1, l, c, lfy, gl);
@@ -191,7 +210,7 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
           h = fma(uq[q * M + b], w, h);
         }
       const size_t off = static_cast<size_t>(cell) * M * N + k;
-      const double d = v - P.uold[off];
+      const double d = v - (k == r ? uold0 : P.uold[off]);
       d2 = fma(d, d, d2);
       finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
       P.unew[off] = v;
@@ -226,42 +245,46 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
     red[2 * groups + 2 * (threadIdx.x >> 6) + 1] = ny_speed;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double sres = 0.0, bad = 0.0;
-    int cnt = 0;
-    for (int k = 0; k < groups; ++k) {
-      sres += red[2 * k];
-      bad += red[2 * k + 1];
-      cnt += s_route[k] ? 1 : 0;
-    }
-    P.res_part[blk] = sres;
-    if (bad > 0.0 || !(ax == ax) || !(ay == ay) || !(dt > 0.0 || last))
-      atomicOr(&C->status, kStNonfinite);
+  if (threadIdx.x < 64) {  // wavefront 0, all lanes: block totals and list appends
+    const int k = threadIdx.x;
+    const int rk = k < groups ? s_route[k] : 0;
     const int slot = blk & (kSlots - 1);
-    if (!P.one_shot) {
-      double mx = 0.0, my = 0.0;
-      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
-        mx = nan_max(mx, red[2 * groups + 2 * w]);
-        my = nan_max(my, red[2 * groups + 2 * w + 1]);
+    if (k == 0) {
+      double sres = 0.0, bad = 0.0;
+      for (int g = 0; g < groups; ++g) {
+        sres += red[2 * g];
+        bad += red[2 * g + 1];
       }
-      atomicMax(&C->amax[P.parity ^ 1][0][slot * kSlotStride], speed_bits(mx));
-      if (P.dim == 2) atomicMax(&C->amax[P.parity ^ 1][1][slot * kSlotStride], speed_bits(my));
-      if (cnt)
-        for (int c = 0; c < kCls; ++c) {
-          int cc = 0;
-          for (int k = 0; k < groups; ++k) cc += (s_route[k] == c + 1) ? 1 : 0;
-          if (!cc) continue;
-          int base = static_cast<int>(
-              atomicAdd(&C->list_len[list_len_index(P.parity ^ 1, c, slot)], static_cast<unsigned>(cc)));
-          for (int k = 0; k < groups; ++k)
-            if (s_route[k] == c + 1) {
-              if (base < P.list_cap[c])
-                P.lists[c][static_cast<size_t>(slot) * P.list_cap[c] + base] = blk * groups + k;
-              ++base;
-            }
+      P.res_part[blk] = sres;
+      if (bad > 0.0 || !(ax == ax) || !(ay == ay) || !(dt > 0.0 || last))
+        atomicOr(&C->status, kStNonfinite);
+      if (!P.one_shot) {
+        double mx = 0.0, my = 0.0;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+          mx = nan_max(mx, red[2 * groups + 2 * w]);
+          my = nan_max(my, red[2 * groups + 2 * w + 1]);
         }
+        atomicMax(&C->amax[P.parity ^ 1][0][slot * kSlotStride], speed_bits(mx));
+        if (P.dim == 2) atomicMax(&C->amax[P.parity ^ 1][1][slot * kSlotStride], speed_bits(my));
+      }
     }
-    if (blk == 0) {
+    if (!P.one_shot)
+      for (int c = 0; c < kCls; ++c) {
+        // groups routed to class c, in group order: one atomic per class
+        const unsigned long long m = __ballot(rk == c + 1);
+        if (m == 0ull) continue;  // uniform
+        int base = 0;
+        if (k == 0)
+          base = static_cast<int>(atomicAdd(&C->list_len[list_len_index(P.parity ^ 1, c, slot)],
+                                            static_cast<unsigned>(__popcll(m))));
+        base = __shfl(base, 0, 64);
+        if (rk == c + 1) {
+          const int pos = base + __popcll(m & ((1ull << k) - 1ull));
+          if (pos < P.list_cap[c])
+            P.lists[c][static_cast<size_t>(slot) * P.list_cap[c] + pos] = blk * groups + k;
+        }
+      }
+    if (blk == 0 && k == 0) {
       C->t[P.parity ^ 1] = last ? P.t_end : t0 + dt;
       C->done[P.parity ^ 1] = last ? 1 : 0;
       C->dt_last = dt;
