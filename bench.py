@@ -7,7 +7,7 @@ nodes and the moment update (plus the device-side time step).  Workload:
 per cell), 20 Gauss-Legendre nodes, Euler entropy, CFL 0.5, t_end = 0.14,
 FP64 throughout.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
@@ -268,8 +268,8 @@ def main():
                     help="also run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (cells would shard "
+              "spatially with a one-cell halo per step)", file=sys.stderr)
         sys.exit(2)
     if args.form == "batch":
         print(json.dumps(batch_form(args)), flush=True)
