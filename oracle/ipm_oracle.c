@@ -29,6 +29,14 @@
  *     descending (gives the prefix property used by per-cell degrees).
  *   - Steady residual (eq:residualSteady): Euclidean norm over all N*m
  *     moments, weighted by the cell volume.
+ *   - Adaptivity (Sec. 5, Alg. ad-IPM): levels are total degrees; the
+ *     indicator is taken on the first conserved variable of the ansatz
+ *     u_s(lambda^T phi) at the cell's current level, right after its dual
+ *     solve; one level per step; the printed thresholds are ordered
+ *     delta_lo < delta_hi (lower below the smaller, raise above the larger);
+ *     one quadrature rule serves every level (its nodes contain those of
+ *     every coarser level trivially), so a neighbour's ansatz is read at
+ *     the shared nodes whatever its level.
  */
 #include "ipm_oracle.h"
 
@@ -403,6 +411,7 @@ struct orc_state {
   double dx, dy, vol;
   double *nodes, *w, *Phi;
   int *Nc;                 /* modes per cell (prefix of the graded basis) */
+  int *deg, *deg_next;     /* total degree per cell: this step, next step */
   double *uhat, *lam, *unew, *nodal; /* [cells][m][N] x3, [cells][Q][m] */
   double *ghost[4];        /* Dirichlet ghost nodal states [Q][m] */
   int *iters;
@@ -677,8 +686,12 @@ orc_state *orc_create(const orc_problem *pb, const signed char *cell_degree,
   S->nodal = (double *)calloc((size_t)S->cells * Q * S->m, sizeof(double));
   S->iters = (int *)calloc(S->cells, sizeof(int));
   S->Nc = (int *)malloc(sizeof(int) * S->cells);
-  for (int c = 0; c < S->cells; ++c)
-    S->Nc[c] = cell_degree ? orc_num_basis(pb->p, cell_degree[c]) : S->N;
+  S->deg = (int *)malloc(sizeof(int) * S->cells);
+  S->deg_next = (int *)malloc(sizeof(int) * S->cells);
+  for (int c = 0; c < S->cells; ++c) {
+    S->deg[c] = cell_degree ? cell_degree[c] : pb->degree;
+    S->Nc[c] = orc_num_basis(pb->p, S->deg[c]);
+  }
 
   int st = 0;
   /* IC (Alg. 1, first loop): uhat_j^0 = <u_IC(x_j, .) phi>_Q at cell centres,
@@ -724,7 +737,7 @@ void orc_destroy(orc_state *S)
 {
   if (!S) return;
   free(S->nodes); free(S->w); free(S->Phi); free(S->uhat); free(S->lam); free(S->unew);
-  free(S->nodal); free(S->iters); free(S->Nc);
+  free(S->nodal); free(S->iters); free(S->Nc); free(S->deg); free(S->deg_next);
   for (int k = 0; k < 4; ++k) free(S->ghost[k]);
   free(S);
 }
@@ -758,6 +771,31 @@ static const double *neighbour(const orc_state *S, int ix, int iy, int side)
   return S->nodal + ((size_t)jy * nx + jx) * S->Q * S->m;
 }
 
+/* DetermineRefinementLevel of Alg. ad-IPM for cell c after its dual solve:
+   the indicator eq:errorIndicator of the first conserved variable of the
+   ansatz u_s(lam^T phi) at the cell's current level d (moments up to degree
+   d and the averages by quadrature, orc_indicator); below delta_lo the cell
+   goes one level down, above delta_hi one level up, kept within
+   [min_degree, degree].  The thresholds are ordered delta_lo < delta_hi
+   (the experiments of Sec. 7 print them the other way round). */
+static int next_level(const orc_state *S, int c)
+{
+  int d = S->deg[c], Q = S->Q, m = S->m;
+  double *u = (double *)malloc(sizeof(double) * Q);
+  double *Sv = (double *)malloc(sizeof(double) * (d > 0 ? d : 1));
+  for (int q = 0; q < Q; ++q) u[q] = S->nodal[((size_t)c * Q + q) * m];
+  int dn = d;
+  if (d >= 1) {
+    orc_indicator(S->pb.p, d, S->pb.quad_per_dim, u, Sv);
+    double ind = Sv[d - 1];
+    if (ind < S->pb.delta_lo && d > S->pb.min_degree) dn = d - 1;
+    else if (ind > S->pb.delta_hi && d < S->pb.degree) dn = d + 1;
+  }
+  free(u);
+  free(Sv);
+  return dn;
+}
+
 /* ------------------------------------------------------------------ */
 /* Time stepping: Alg. 1 (IPM) and Alg. 2 (one-shot IPM)                */
 /* ------------------------------------------------------------------ */
@@ -785,6 +823,11 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
           st |= ORC_ST_REALIZABILITY;
       }
       scratch_free(&w);
+    }
+    /* Alg. ad-IPM: the level of the next step from the new dual state */
+    if (S->pb.adapt) {
+#pragma omp parallel for schedule(static)
+      for (int c = 0; c < S->cells; ++c) S->deg_next[c] = next_level(S, c);
     }
     /* time step from the largest wave speed over all cells and nodes */
     double ax = 0.0, ay = 0.0;
@@ -833,7 +876,9 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
           for (int a = 0; a < m; ++a) acc[q * m + a] -= dt / S->dy * (gr[a] - gl[a]);
         }
       }
-      project(S, S->Nc[c], acc, S->unew + (size_t)c * n);
+      /* adaptive: eq:adaptiveFVUpdate, the projection on the new level */
+      int Nn = S->pb.adapt ? orc_num_basis(S->pb.p, S->deg_next[c]) : S->Nc[c];
+      project(S, Nn, acc, S->unew + (size_t)c * n);
       free(acc);
     }
     /* steady residual eq:residualSteady, fixed summation order */
@@ -851,6 +896,16 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
     double *tmp = S->uhat;
     S->uhat = S->unew;
     S->unew = tmp;
+    /* adaptive: the dual of the next step keeps the modes of the new level
+       (padded with zeros when the level rises) */
+    if (S->pb.adapt)
+      for (int c = 0; c < S->cells; ++c) {
+        int Nn = orc_num_basis(S->pb.p, S->deg_next[c]);
+        for (int a = 0; a < m; ++a)
+          for (int i = Nn; i < S->N; ++i) S->lam[(size_t)c * n + a * S->N + i] = 0.0;
+        S->Nc[c] = Nn;
+        S->deg[c] = S->deg_next[c];
+      }
     S->info.t = last ? S->pb.t_end : S->info.t + dt;
     S->info.dt = dt;
     S->info.amax = S->dim == 2 ? (ax > ay ? ax : ay) : ax;
@@ -890,6 +945,11 @@ void orc_set_dual(orc_state *S, const double *in)
 }
 
 void orc_get_iters(const orc_state *S, int *out) { memcpy(out, S->iters, sizeof(int) * S->cells); }
+
+void orc_get_degrees(const orc_state *S, signed char *out)
+{
+  for (int c = 0; c < S->cells; ++c) out[c] = (signed char)S->deg[c];
+}
 
 int orc_get_nodal(const orc_state *S, double *out)
 {

@@ -58,6 +58,13 @@ typedef struct {
   int bc[4];             /* x-, x+, y-, y+ : ORC_BC_* */
   double cfl, t_end, tau, steady_eps;
   int max_newton, one_shot;
+  /* dynamic adaptivity (Sec. 5, Alg. ad-IPM): after each dual solve a cell
+     moves one level (total degree) down when the indicator of its ansatz at
+     its level is below delta_lo, one up when it is above delta_hi, within
+     [min_degree, degree]; the moment update projects on the new level and
+     the dual drops the modes above it.  adapt = 0: levels stay fixed. */
+  int adapt, min_degree;
+  double delta_lo, delta_hi;
 } orc_problem;
 
 typedef struct {
@@ -108,6 +115,7 @@ void orc_set_moments(orc_state *S, const double *in);
 void orc_get_dual(const orc_state *S, double *out /*[cells][m][N]*/);
 void orc_set_dual(orc_state *S, const double *in);
 void orc_get_iters(const orc_state *S, int *out /*[cells]*/);
+void orc_get_degrees(const orc_state *S, signed char *out /*[cells] current total degree*/);
 int orc_get_nodal(const orc_state *S, double *out /*[cells][Q][m]*/);
 void orc_tables(const orc_state *S, double *nodes, double *w, double *Phi);
 

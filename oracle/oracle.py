@@ -33,6 +33,8 @@ class Problem(C.Structure):
         ("cfl", C.c_double), ("t_end", C.c_double), ("tau", C.c_double),
         ("steady_eps", C.c_double),
         ("max_newton", C.c_int), ("one_shot", C.c_int),
+        ("adapt", C.c_int), ("min_degree", C.c_int),
+        ("delta_lo", C.c_double), ("delta_hi", C.c_double),
     ]
 
 
@@ -96,6 +98,8 @@ def load():
         getattr(lib, nm).restype = None
     lib.orc_get_iters.argtypes = [C.c_void_p, ip]
     lib.orc_get_iters.restype = None
+    lib.orc_get_degrees.argtypes = [C.c_void_p, P(C.c_byte)]
+    lib.orc_get_degrees.restype = None
     lib.orc_get_nodal.argtypes = [C.c_void_p, dp]
     lib.orc_tables.argtypes = [C.c_void_p, dp, dp, dp]
     lib.orc_tables.restype = None
@@ -206,6 +210,10 @@ def make_problem(spec):
     pb.steady_eps = spec.get("steady_eps", 0.0)
     pb.max_newton = spec.get("max_newton", 100)
     pb.one_shot = int(spec.get("one_shot", 0))
+    pb.adapt = int(spec.get("adapt", 0))
+    pb.min_degree = spec.get("min_degree", 1)
+    pb.delta_lo = spec.get("delta_lo", 0.0)
+    pb.delta_hi = spec.get("delta_hi", 0.0)
     return pb
 
 
@@ -280,6 +288,12 @@ class Oracle:
     def iters(self):
         out = np.zeros(self.cells, dtype=np.int32)
         self._lib.orc_get_iters(self._h, _ptr(out, C.c_int))
+        return out
+
+    def degrees(self):
+        """Current total degree (refinement level) of every cell."""
+        out = np.zeros(self.cells, dtype=np.int8)
+        self._lib.orc_get_degrees(self._h, out.ctypes.data_as(C.POINTER(C.c_byte)))
         return out
 
     def nodal(self):
