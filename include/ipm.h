@@ -102,6 +102,20 @@ typedef struct {
   const double *ic_moments; /* [cells][m][N] initial moments (used if ic_nodal == NULL) */
   const double *ic_dual;    /* optional [cells][m][N] warm start of the dual (resume) */
   const double *dirichlet;  /* [4][Q][m] nodal ghost states of Dirichlet sides, or NULL */
+  /* Dynamic adaptivity (Sec. 5, Alg. ad-IPM).  adapt = 1: after its dual
+     solve every cell takes the smoothness indicator eq:errorIndicator of the
+     first conserved variable of its ansatz at its current level (levels are
+     total degrees); below delta_lo it moves one level down, above delta_hi
+     one level up, within [min_degree, degree].  The moment update projects
+     on the new level (eq:adaptiveFVUpdate) and the dual keeps the modes of
+     the new level (zero-padded when it rises).  The levels start at
+     cell_degree (NULL: degree).  Needs min_degree >= 1, delta_lo <= delta_hi
+     and quad_per_dim >= degree + 1 (the indicator's averages are then exact
+     sums of squared modes); the classical mode only (one_shot = 0).
+     adapt = 0: the per-cell degrees stay fixed and these fields are ignored. */
+  int adapt;
+  int min_degree;
+  double delta_lo, delta_hi;
 } ipm_problem;
 
 typedef struct {
@@ -217,6 +231,11 @@ ipm_status ipm_moments(ipm_ctx *ctx, int id, double *out, size_t out_len, int ou
 
 /* Current dual state [cells][m][N] (checkpoint; pass back as ic_dual). */
 ipm_status ipm_dual(ipm_ctx *ctx, int id, double *out, size_t out_len, int out_is_device);
+
+/* Current total degree (refinement level) of every cell of a problem:
+   host out [cells], capacity out_len.  Waits for the context's stream.  For
+   a problem with fixed degrees these are the degrees it was created with. */
+ipm_status ipm_cell_degrees(ipm_ctx *ctx, int id, int8_t *out, size_t out_len);
 
 /* Sizes of a problem: conserved variables, basis functions, nodes, cells. */
 ipm_status ipm_problem_sizes(ipm_ctx *ctx, int id, int *m, int *N, int *Q, int *cells);

@@ -45,6 +45,8 @@ class Problem(C.Structure):
         ("bc", C.c_int * 4),
         ("ic_nodal", C.POINTER(C.c_double)), ("ic_moments", C.POINTER(C.c_double)),
         ("ic_dual", C.POINTER(C.c_double)), ("dirichlet", C.POINTER(C.c_double)),
+        ("adapt", C.c_int), ("min_degree", C.c_int),
+        ("delta_lo", C.c_double), ("delta_hi", C.c_double),
     ]
 
 
@@ -68,7 +70,8 @@ class Request(C.Structure):
 EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm_basis_table",
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
-           "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_last_error"]
+           "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_cell_degrees",
+           "ipm_last_error"]
 
 _lib = None
 
@@ -102,6 +105,7 @@ def load(path=None):
     lib.ipm_serve.argtypes = [vp, C.c_int, P(Request), C.c_int, C.c_int]
     lib.ipm_select_degrees.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double,
                                        P(C.c_int8)]
+    lib.ipm_cell_degrees.argtypes = [vp, C.c_int, P(C.c_int8), C.c_size_t]
     lib.ipm_last_error.argtypes = [vp]
     lib.ipm_last_error.restype = C.c_char_p
     _lib = lib
@@ -165,6 +169,10 @@ def problem_struct(spec, keep):
     pb.max_newton = spec.get("max_newton", 100)
     pb.one_shot = int(spec.get("one_shot", 0))
     pb.precision = PREC[spec.get("precision", "fp64")]
+    pb.adapt = int(spec.get("adapt", 0))
+    pb.min_degree = spec.get("min_degree", 1)
+    pb.delta_lo = spec.get("delta_lo", 0.0)
+    pb.delta_hi = spec.get("delta_hi", 0.0)
     pb.nx = spec["nx"]
     pb.ny = spec.get("ny", 1)
     pb.x0, pb.x1 = spec["x0"], spec["x1"]
@@ -304,6 +312,14 @@ class Context:
         m, N, _, cells = self.sizes(pid)
         out = np.zeros((cells, m, N))
         self._check(self.lib.ipm_dual(self.h, pid, out.ctypes.data, out.size, 0))
+        return out
+
+    def degrees(self, pid):
+        """Current total degree (refinement level) of every cell."""
+        _, _, _, cells = self.sizes(pid)
+        out = np.zeros(cells, dtype=np.int8)
+        self._check(self.lib.ipm_cell_degrees(self.h, pid, out.ctypes.data_as(C.POINTER(C.c_int8)),
+                                              cells))
         return out
 
     def release(self, pid):

@@ -39,7 +39,8 @@ struct DualClass {
   int T = 0;                // > 0: workgroup kernel with T x T tiles
   int waves = 4;            // small kernel: wavefronts per block
   size_t lds = 0;
-  int count = 0;            // cells of the class
+  int count = 0;            // cells the class plans for (all cells when levels adapt)
+  int order_len = 0;        // cells of the class at set-up (length of d_order)
   int cap = 0;              // list capacity per slot
   int* d_lists = nullptr;   // [2][64][cap] Newton lists by step parity
   int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
@@ -57,6 +58,9 @@ struct Problem {
   double dx = 1.0, dy = 1.0, vol = 1.0;
   ClosureParams cp{};
   bool uneven = false;
+  // dynamic adaptivity: levels move between min_degree and degree
+  int adapt = 0, min_degree = 1;
+  double delta_lo = 0.0, delta_hi = 0.0;
   double* d_phi = nullptr;
   double* d_wphi = nullptr;
   double* d_u[2] = {nullptr, nullptr};
@@ -65,7 +69,9 @@ struct Problem {
   double* d_ghost = nullptr;
   double* d_res = nullptr;
   unsigned long long* d_blk = nullptr;
-  int8_t* d_cellN = nullptr;
+  // modes per cell read by the steps of each parity (one buffer when fixed;
+  // adaptive: the update of a step writes the other parity's buffer)
+  int8_t* d_cellN[2] = {nullptr, nullptr};
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;    // device bytes allocated
@@ -326,9 +332,10 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN, P->d_ctrl};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
   for (DualClass& c : P->cls) {
     if (c.d_lists) (void)hipFree(c.d_lists);
     if (c.d_order) (void)hipFree(c.d_order);
@@ -469,8 +476,8 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
   } else {
     d.list_cap = 0;
     d.order = D.d_order;
-    d.order_len = D.count;
-    items = D.count;
+    d.order_len = D.order_len;
+    items = D.order_len;
     d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
   }
   if (items == 0) return IPM_OK;
@@ -513,7 +520,7 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.nx = P.nx;
   u.ny = P.ny;
   u.dim = P.dim;
-  u.cellN = P.d_cellN;
+  u.cellN = P.d_cellN[parity];
   u.nodal = P.d_nodal;
   u.ghost = P.d_ghost;
   u.uold = P.d_u[parity];
@@ -536,13 +543,21 @@ UpdateParams update_params(const Problem& P, int parity) {
     u.lists[c] = D.cap > 0 ? D.d_lists + static_cast<size_t>(parity ^ 1) * kSlots * D.cap : nullptr;
     u.list_cap[c] = D.cap;
   }
+  u.adapt = P.adapt;
+  u.p = P.p;
+  u.deg_min = P.min_degree;
+  u.deg_max = P.degree;
+  u.delta_lo = P.delta_lo;
+  u.delta_hi = P.delta_hi;
+  u.cellN_next = P.adapt ? P.d_cellN[parity ^ 1] : nullptr;
+  u.lam = P.d_lam;
   return u;
 }
 
 ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   const int parity = static_cast<int>(P.step_index & 1);
   DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
-                             P.d_cellN, P.d_ctrl, P.d_blk);
+                             P.d_cellN[parity], P.d_ctrl, P.d_blk);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
   if (ctx->timing) {
     while (ctx->ev.size() < ctx->ev_used + 4) {
@@ -675,7 +690,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
       Problem& P = *get(ctx, id);
       const int parity = static_cast<int>((P.step_index + ph) & 1);
       DualParams d = dual_params(P, 0, parity, P.d_u[parity], P.d_lam, P.d_nodal, P.cells,
-                                 P.d_cellN, P.d_ctrl, P.d_blk);
+                                 P.d_cellN[parity], P.d_ctrl, P.d_blk);
       bool first = true;
       for (int c = 0; c < kCls; ++c) {
         const DualClass& D = P.cls[c];
@@ -694,8 +709,8 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         } else {
           dc.list_cap = 0;
           dc.order = D.d_order;
-          dc.order_len = D.count;
-          items = D.count;
+          dc.order_len = D.order_len;
+          items = D.order_len;
         }
         const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
@@ -975,6 +990,15 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
   for (int s = 0; s < sides; ++s) any_dir |= pb->bc[s] == IPM_BC_DIRICHLET;
   if (any_dir && !pb->dirichlet) return fail(ctx, IPM_E_ARG, "Dirichlet sides need dirichlet states");
   if (!pb->ic_nodal && !pb->ic_moments) return fail(ctx, IPM_E_ARG, "need ic_nodal or ic_moments");
+  if (pb->adapt) {
+    if (pb->min_degree < 1 || pb->min_degree > pb->degree)
+      return fail(ctx, IPM_E_ARG, "adaptivity needs 1 <= min_degree <= degree");
+    if (!(pb->delta_lo <= pb->delta_hi))
+      return fail(ctx, IPM_E_ARG, "adaptivity needs delta_lo <= delta_hi");
+    if (pb->quad_per_dim < pb->degree + 1)
+      return fail(ctx, IPM_E_ARG, "adaptivity needs quad_per_dim >= degree + 1");
+    if (pb->one_shot) return fail(ctx, IPM_E_ARG, "adaptivity runs in the classical mode (one_shot = 0)");
+  }
   return IPM_OK;
 }
 
@@ -1029,7 +1053,9 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
   return sizeof(double) * (3 * cells * n + cells * Q * M + 2 * static_cast<size_t>(Q) * (N + 64) +
                            4 * static_cast<size_t>(Q) * M + cells / 8 + 64) +
          cells + 2 * (cells + static_cast<size_t>(kCls) * kSlots * 16) * sizeof(int) + cells * sizeof(int) +
-         sizeof(StepCtrl);
+         sizeof(StepCtrl) +
+         (pb->adapt ? cells + static_cast<size_t>(pb->degree) * 2 * (cells + kSlots * 16) * sizeof(int)
+                    : 0);
 }
 
 ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
@@ -1104,15 +1130,20 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.um = pb->u_minus;
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
+  P.adapt = pb->adapt ? 1 : 0;
+  P.min_degree = pb->min_degree;
+  P.delta_lo = pb->delta_lo;
+  P.delta_hi = pb->delta_hi;
   std::vector<int8_t> cellN;
   int counts[kCls] = {};
   std::vector<int> cell_cls;
-  if (pb->cell_degree) {
+  const int lo_deg = P.adapt ? P.min_degree : 0;
+  if (pb->cell_degree || P.adapt) {
     cellN.resize(P.cells);
     cell_cls.resize(P.cells);
     for (int c = 0; c < P.cells; ++c) {
-      const int dg = pb->cell_degree[c];
-      if (dg < 0 || dg > pb->degree) return fail(ctx, IPM_E_ARG, "cell_degree out of range");
+      const int dg = pb->cell_degree ? pb->cell_degree[c] : pb->degree;
+      if (dg < lo_deg || dg > pb->degree) return fail(ctx, IPM_E_ARG, "cell_degree out of range");
       cellN[c] = static_cast<int8_t>(binom_basis(pb->p, dg));
       cell_cls[c] = size_class(cellN[c] * P.M);
       ++counts[cell_cls[c]];
@@ -1121,8 +1152,14 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   } else {
     counts[size_class(P.M * P.N)] = P.cells;
   }
-  st = plan(ctx, P, counts);
+  int plan_counts[kCls];
+  for (int c = 0; c < kCls; ++c) plan_counts[c] = counts[c];
+  if (P.adapt)  // every level may hold every cell
+    for (int dg = P.min_degree; dg <= P.degree; ++dg)
+      plan_counts[size_class(binom_basis(pb->p, dg) * P.M)] = P.cells;
+  st = plan(ctx, P, plan_counts);
   if (st != IPM_OK) return st;
+  for (int c = 0; c < kCls; ++c) P.cls[c].order_len = counts[c];
 
   const size_t fp = ipm_problem_footprint(pb);
   if (ctx->budget && ctx->used + fp > ctx->budget)
@@ -1174,10 +1211,12 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long));
   for (DualClass& D : P.cls) {
     if (D.cap > 0) ALLOC(D.d_lists, 2 * static_cast<size_t>(kSlots) * D.cap * sizeof(int));
-    if (P.uneven && D.count > 0) ALLOC(D.d_order, static_cast<size_t>(D.count) * sizeof(int));
+    if (P.uneven && D.order_len > 0) ALLOC(D.d_order, static_cast<size_t>(D.order_len) * sizeof(int));
   }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
-  if (P.uneven) ALLOC(P.d_cellN, static_cast<size_t>(P.cells));
+  if (P.uneven) ALLOC(P.d_cellN[0], static_cast<size_t>(P.cells));
+  if (P.adapt) ALLOC(P.d_cellN[1], static_cast<size_t>(P.cells));
+  else P.d_cellN[1] = P.d_cellN[0];
 #undef ALLOC
   hipStream_t s = ctx->stream;
 #define CHK(expr)                                                                          \
@@ -1190,7 +1229,9 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   CHK(hipMemcpyAsync(P.d_wphi, wphip.data(), wphip.size() * sizeof(double), hipMemcpyHostToDevice, s));
   std::vector<std::vector<int>> orders(kCls);
   if (P.uneven) {
-    CHK(hipMemcpyAsync(P.d_cellN, cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
+    CHK(hipMemcpyAsync(P.d_cellN[0], cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
+    if (P.adapt)
+      CHK(hipMemcpyAsync(P.d_cellN[1], cellN.data(), cellN.size(), hipMemcpyHostToDevice, s));
     for (int c = 0; c < P.cells; ++c) orders[cell_cls[c]].push_back(c);
     for (int k = 0; k < kCls; ++k)
       if (P.cls[k].d_order)
@@ -1220,7 +1261,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   sp.Q = P.Q;
   sp.kp = P.kp;
   sp.cells = P.cells;
-  sp.cellN = P.d_cellN;
+  sp.cellN = P.d_cellN[0];
   sp.ic_nodal = pb->ic_nodal ? d_in : nullptr;
   sp.ic_moments = pb->ic_nodal ? nullptr : d_in;
   sp.ic_dual = d_dual;
@@ -1236,7 +1277,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   }
   // converge the initial dual (setup mode of the dual kernel)
   {
-    DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN, P.d_ctrl,
+    DualParams d = dual_params(P, 1, 0, P.d_u[0], P.d_lam, P.d_nodal, P.cells, P.d_cellN[0], P.d_ctrl,
                                P.d_blk);
     st = launch_dual_classes(ctx, P, d, false);
     if (st != IPM_OK) return cleanup(st);
@@ -1414,6 +1455,31 @@ ipm_status ipm_dual(ipm_ctx* ctx, int id, double* out, size_t out_len, int out_i
                              out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                              ctx->stream));
   if (!out_is_device) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return IPM_OK;
+}
+
+ipm_status ipm_cell_degrees(ipm_ctx* ctx, int id, int8_t* out, size_t out_len) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_cell_degrees: unknown problem id");
+  if (!out || out_len < static_cast<size_t>(P->cells))
+    return fail(ctx, IPM_E_ARG, "ipm_cell_degrees: output too small");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (!P->uneven) {
+    std::memset(out, P->degree, static_cast<size_t>(P->cells));
+    return IPM_OK;
+  }
+  StepCtrl hc;
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<int8_t> modes(P->cells);
+  HIPCHK(ctx, hipMemcpyAsync(modes.data(), P->d_cellN[hc.steps & 1], modes.size(),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (int c = 0; c < P->cells; ++c) {
+    int d = 0;
+    while (binom_basis(P->p, d) < modes[c]) ++d;
+    out[c] = static_cast<int8_t>(d);
+  }
   return IPM_OK;
 }
 

@@ -17,6 +17,11 @@
 // nodal ansatz, and their wave speeds enter the next step's slots here;
 // the others are appended to the next step's Newton lists.
 //
+// With dynamic adaptivity (Sec. 5, Alg. ad-IPM) the same pass picks each
+// cell's level for the next step from its ansatz and projects the update on
+// that level; the step's dual kernels read the levels of their own parity,
+// the update writes the other parity's.
+//
 // Step bookkeeping avoids device-scope fences: every block derives the same
 // dt from the 64 speed slots; block 0 alone advances t, the step count and
 // the stop flag of the next step parity; the residual is written as one
@@ -45,7 +50,21 @@ struct UpdateParams {
   int list_cap[kCls];
   StepCtrl* ctrl;
   int parity;
+  // dynamic adaptivity (adapt = 1): the next step's level of every cell goes
+  // to cellN_next, and a lowered cell's dual loses the modes above its level
+  int adapt, p, deg_min, deg_max;
+  double delta_lo, delta_hi;
+  int8_t* __restrict__ cellN_next;   // [cells] modes of the next step
+  double* __restrict__ lam;          // [cells][M][N]
 };
+
+// number of basis functions of total degree <= d in p dimensions,
+// binomial(d + p, p) (eq:numberBasisFcts); 0 for d = -1
+__device__ __forceinline__ int basis_count(int p, int d) {
+  int n = 1;
+  for (int k = 1; k <= p; ++k) n = n * (d + k) / k;
+  return n;
+}
 
 template <int M>
 __device__ __forceinline__ const double* neighbour_nodal(const UpdateParams& P, int ix, int iy,
@@ -197,13 +216,49 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
     }
     wave_sync();
     const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
+    // Alg. ad-IPM: the indicator eq:errorIndicator of the first variable of
+    // the ansatz at the cell's level d moves the cell one level down or up.
+    // The basis is orthonormal, so the averages of the squared truncations
+    // are sums of squared ansatz moments (exact for a rule of >= d+1 points
+    // per dimension).  The moments below are projected on the new level
+    // (eq:adaptiveFVUpdate); a lowered cell drops its dual's top modes and
+    // always goes to Newton.
+    int Nn = Nc;
+    bool lowered = false;
+    if (P.adapt) {
+      int d = 0;
+      while (basis_count(P.p, d) < Nc) ++d;
+      const int Nlo = basis_count(P.p, d - 1);
+      double top = 0.0, all = 0.0;
+      for (int i = r; i < Nc; i += G) {
+        double h = 0.0;
+        for (int q = 0; q < Q; ++q) h = fma(uq[q * M], wphiL[q * kp + i], h);
+        all = fma(h, h, all);
+        if (i >= Nlo) top = fma(h, h, top);
+      }
+      top = group_sum<G>(top);
+      all = group_sum<G>(all);
+      const double ind = top / all;
+      int dn = d;
+      if (ind < P.delta_lo && d > P.deg_min) dn = d - 1;
+      else if (ind > P.delta_hi && d < P.deg_max) dn = d + 1;
+      Nn = basis_count(P.p, dn);
+      if (r == 0) P.cellN_next[cell] = static_cast<int8_t>(Nn);
+      if (Nn < Nc) {
+        lowered = true;
+        for (int k = r; k < M * N; k += G) {
+          const int i = k % N;
+          if (i >= Nn && i < Nc) P.lam[static_cast<size_t>(cell) * M * N + k] = 0.0;
+        }
+      }
+    }
     double d2 = 0.0, gsq[M];
 #pragma unroll
     for (int b = 0; b < M; ++b) gsq[b] = 0.0;
     for (int k = r; k < M * N; k += G) {
       const int b = k / N, i = k % N;
       double v = 0.0, h = 0.0;
-      if (i < Nc)
+      if (i < Nn)
         for (int q = 0; q < Q; ++q) {
           const double w = wphiL[q * kp + i];
           v = fma(ut[q * M + b], w, v);
@@ -225,7 +280,7 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
 #pragma unroll
       for (int b = 0; b < M; ++b) resn += sqrt(group_sum<G>(gsq[b]));
       // NaN routes to Newton, which reports it; the value is the list class + 1
-      route = (resn < 0.5 * P.tau) ? 0 : 1 + size_class(Nc * M);
+      route = (resn < 0.5 * P.tau && !lowered) ? 0 : 1 + size_class(Nn * M);
     }
   }
   // speeds of the cells whose nodal ansatz carries over to the next step

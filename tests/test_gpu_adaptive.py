@@ -1,0 +1,135 @@
+"""GPU parity of dynamic adaptivity (Sec. 5, Alg. ad-IPM) through the C ABI:
+levels bitwise equal to the oracle's after every checked step, moments
+within the FP64 bound (normwise relative L1 per variable <= 1e-10), the
+batched path bitwise equal to stepping alone, and the argument checks."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_09238_amd import workloads as W
+
+from .conftest import parity
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _adaptive(spec, lo, hi, dmin):
+    s = dict(spec)
+    s.update(adapt=1, min_degree=dmin, delta_lo=lo, delta_hi=hi)
+    return s
+
+
+def _make(ctx, spec, cd=None):
+    from paper_1912_09238_amd import binding
+    nodes, _ = binding.quadrature(spec["p"], spec["quad_per_dim"])
+    kw = {"cell_degree": cd} if cd is not None else {}
+    return ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes), **kw)
+
+
+def _compare(ctx, orc, spec, chunks, cd=None):
+    """Step GPU and oracle side by side; after each chunk of steps compare
+    the levels (bitwise) and the moments."""
+    _say("gpu case: adaptive %s nx=%d ny=%d M=%d qpd=%d p=%d chunks=%s" % (
+        spec["name"], spec["nx"], spec.get("ny", 1), spec["degree"], spec["quad_per_dim"],
+        spec["p"], chunks))
+    pid = _make(ctx, spec, cd)
+    kw = {"cell_degree": cd} if cd is not None else {}
+    o = orc.Oracle(spec, ic_fn=lambda nd: W.ic_nodal(spec, nd), **kw)
+    moved = 0
+    prev = o.degrees()
+    try:
+        for k in chunks:
+            info = ctx.step(pid, k, wait=True)[0]
+            oinfo = o.step(k)
+            assert info["status"] == 0, info
+            assert oinfo["status"] == 0, oinfo
+            assert info["steps"] == oinfo["steps"]
+            dg, od = ctx.degrees(pid), o.degrees()
+            assert np.array_equal(dg, od), np.nonzero(dg != od)
+            moved += int(np.sum(od != prev))
+            prev = od
+            err = parity(ctx.moments(pid), o.moments())
+            _say("  step %d: levels %s  parity %s" % (
+                info["steps"], np.bincount(od, minlength=spec["degree"] + 1),
+                np.array2string(err, precision=2)))
+            assert np.all(err <= TOL), err
+    finally:
+        ctx.release(pid)
+    return moved, info, oinfo
+
+
+def test_adaptive_sod(gpu_ctx, orc):
+    spec = _adaptive(W.sod(nx=250, degree=9, qpd=20), 2e-5, 2e-4, 2)
+    moved, info, oinfo = _compare(gpu_ctx, orc, spec, [1, 4, 15, 20])
+    assert moved > 200
+    assert abs(info["newton_iters"] - oinfo["newton_iters"]) <= 0.02 * oinfo["newton_iters"]
+
+
+def test_adaptive_sod_full_size(gpu_ctx, orc):
+    spec = _adaptive(W.sod(), 2e-5, 2e-4, 2)  # 8192 cells, levels 2..9
+    moved, _, _ = _compare(gpu_ctx, orc, spec, [3, 5])
+    assert moved > 8000
+
+
+def test_adaptive_burgers_full_run(gpu_ctx, orc):
+    spec = _adaptive(W.burgers_shock(nx=200, degree=4, qpd=10), 1e-6, 1e-4, 1)
+    moved, info, _ = _compare(gpu_ctx, orc, spec, [2, 100])
+    assert info["done"] == 1 and info["steps"] == 9 and moved > 100
+
+
+def test_adaptive_2d_p2(gpu_ctx, orc):
+    spec = _adaptive(W.bump2d(n=24, degree=5, qpd=8, p=2), 1e-8, 1e-4, 1)
+    spec["ny"] = 20  # ragged: 480 cells
+    moved, _, _ = _compare(gpu_ctx, orc, spec, [2, 4, 6])
+    assert moved > 400
+
+
+def test_adaptive_2d_p3_workgroup_classes(gpu_ctx, orc):
+    """p = 3: level 3 (80 unknowns) runs on the workgroup-per-cell kernel;
+    initial levels drawn at random."""
+    spec = _adaptive(W.bump2d(n=16, degree=4, qpd=5, p=3, v1_spread=0.2), 1e-6, 1e-4, 1)
+    cd = np.random.default_rng(3).integers(1, 5, size=256).astype(np.int8)
+    moved, _, _ = _compare(gpu_ctx, orc, spec, [1, 3, 6], cd=cd)
+    assert moved > 100
+
+
+def test_adaptive_batched_equals_alone(gpu_ctx):
+    specs = [(_adaptive(W.sod(nx=300, degree=9, qpd=20, t_end=0.0), 2e-5, 2e-4, 2), None),
+             (_adaptive(W.burgers_shock(nx=150, degree=4, qpd=10, t_end=0.0), 1e-6, 1e-4, 1),
+              None),
+             (W.sod(nx=200, degree=5, qpd=8, t_end=0.0), None)]
+    _say("gpu case: adaptive batch of %d problems vs one by one" % len(specs))
+    alone = []
+    for spec, cd in specs:
+        pid = _make(gpu_ctx, spec, cd)
+        gpu_ctx.step(pid, 17, wait=True)
+        alone.append((gpu_ctx.moments(pid), gpu_ctx.degrees(pid)))
+        gpu_ctx.release(pid)
+    ids = [_make(gpu_ctx, spec, cd) for spec, cd in specs]
+    gpu_ctx.step(ids[0], 1, wait=True)  # mixed step parities in the batch
+    gpu_ctx.step(ids, 6, wait=True)
+    gpu_ctx.step(ids, 10, wait=True)
+    gpu_ctx.step(ids[1:], 1, wait=True)
+    for k, pid in enumerate(ids):
+        assert np.array_equal(gpu_ctx.moments(pid), alone[k][0]), k
+        assert np.array_equal(gpu_ctx.degrees(pid), alone[k][1]), k
+        gpu_ctx.release(pid)
+
+
+@pytest.mark.parametrize("bad", [dict(min_degree=0), dict(min_degree=10),
+                                 dict(delta_lo=1e-3, delta_hi=1e-4), dict(one_shot=1),
+                                 dict(quad_per_dim=9)])
+def test_adaptive_argument_errors(gpu_ctx, bad):
+    from paper_1912_09238_amd import binding
+    spec = _adaptive(W.sod(nx=16, degree=9, qpd=20), 2e-5, 2e-4, 2)
+    spec.update(bad)
+    with pytest.raises(binding.IpmError) as e:
+        _make(gpu_ctx, spec)
+    assert e.value.code == -1
