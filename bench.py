@@ -240,11 +240,126 @@ def serve_form(args):
     }
 
 
+def adapt_form(args):
+    """Adaptive form (Sec. 5, Alg. ad-IPM): levels (total degrees) move every
+    step by the smoothness indicator of the density, one level at a time.
+    Main line: the 2D Euler bump on a periodic 512 x 512 grid, two
+    uncertainties, levels 1..5 (3..21 modes, 12..84 unknowns per cell),
+    8 x 8 nodes, thresholds 1e-5 / 1e-4 (those of the paper's 2D study),
+    against the fixed degree 5 over the same steps; relative L1 difference of
+    E and Var of every conserved variable.  Also: whole Sod trajectories
+    (8192 cells, levels 2..9, thresholds 2e-5 / 2e-4) against degree 9."""
+    import torch
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    rel = lambda a, b: float(np.abs(a - b).sum() / np.abs(b).sum())
+    # ---- 2D bump: fixed steps
+    base = W.bump2d(n=args.prec_n, degree=5, qpd=8, p=2)
+    spec = dict(base, adapt=1, min_degree=1, delta_lo=1e-5, delta_hi=1e-4)
+    nodes, _ = binding.quadrature(2, 8)
+    ic = W.ic_nodal(base, nodes)
+    cells = base["nx"] * base["ny"]
+    res = {}
+    for name, sp in (("fixed", base), ("adaptive", spec)):
+        pid = ctx.set_problem(sp, ic_nodal=ic)
+        ctx.step(pid, args.prec_warmup, wait=True)
+        b = ctx.step(pid, 0, wait=True)[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(pid, args.prec_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        a = ctx.step(pid, 0, wait=True)[0]
+        assert a["status"] == 0, a
+        dg = ctx.degrees(pid)
+        res[name] = {"value": cells * args.prec_steps / el, "ms_per_step": el / args.prec_steps * 1e3,
+                     "kbar": (a["newton_iters"] - b["newton_iters"]) / (cells * args.prec_steps),
+                     "moments": ctx.moments(pid), "levels": np.bincount(dg, minlength=6)}
+        ctx.release(pid)
+        print("adaptive form, 2D: %s %.4g cell-updates/s" % (name, res[name]["value"]),
+              file=sys.stderr, flush=True)
+    mf, ma = res["fixed"]["moments"], res["adaptive"]["moments"]
+    lv = res["adaptive"]["levels"]
+    n_of = np.array([(d + 1) * (d + 2) // 2 for d in range(6)]) * 4
+    # ---- Sod: whole trajectories
+    sbase = W.sod()
+    sspec = dict(sbase, adapt=1, min_degree=2, delta_lo=2e-5, delta_hi=2e-4)
+    snodes, _ = binding.quadrature(1, sbase["quad_per_dim"])
+    sic = W.ic_nodal(sbase, snodes)
+    warm = ctx.set_problem(sspec, ic_nodal=sic)
+    ctx.step(warm, 50, wait=True)
+    ctx.release(warm)
+    sod = {}
+    for name, sp in (("fixed", sbase), ("adaptive", sspec)):
+        pid = ctx.set_problem(sp, ic_nodal=sic)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            ctx.step(pid, 1024)
+            info = ctx.query(pid)
+            if info["done"]:
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert info["status"] == 0, info
+        sod[name] = {"seconds": el, "steps": info["steps"], "moments": ctx.moments(pid),
+                     "value": sbase["nx"] * info["steps"] / el}
+        ctx.release(pid)
+    ctx.close()
+    sf, sa = sod["fixed"]["moments"], sod["adaptive"]["moments"]
+    out = {
+        "metric": METRIC, "value": res["adaptive"]["value"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.prec_steps, "warmup": args.prec_warmup,
+        "ms_per_step": res["adaptive"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "euler2d_bump_%dx%d_adaptive_deg1to5_q64_fp64" % (
+                       args.prec_n, args.prec_n),
+                   "cells": cells, "delta_lo": 1e-5, "delta_hi": 1e-4, "levels": [1, 5],
+                   "parallelism": "single-gpu"},
+        "fixed_degree5": {"value": res["fixed"]["value"], "ms_per_step": res["fixed"]["ms_per_step"],
+                          "kbar": res["fixed"]["kbar"]},
+        "speedup_vs_fixed": res["adaptive"]["value"] / res["fixed"]["value"],
+        "kbar": res["adaptive"]["kbar"],
+        "final_levels": {str(k): int(v) for k, v in enumerate(lv) if v},
+        "mean_unknowns_per_cell": float((lv * n_of).sum() / lv.sum()),
+        "rel_l1_vs_fixed": {v: {"E": rel(ma[:, k, 0], mf[:, k, 0]),
+                                "Var": rel(np.sum(ma[:, k, 1:] ** 2, axis=1),
+                                           np.sum(mf[:, k, 1:] ** 2, axis=1))}
+                            for k, v in enumerate(("rho", "rho_u", "rho_v", "E"))},
+        "sod_trajectory": {
+            "workload": "sod1d_nx8192_adaptive_deg2to9_q20 vs degree 9, t_end 0.14",
+            "adaptive": {"seconds": sod["adaptive"]["seconds"], "steps": sod["adaptive"]["steps"],
+                         "value": sod["adaptive"]["value"]},
+            "fixed": {"seconds": sod["fixed"]["seconds"], "steps": sod["fixed"]["steps"],
+                      "value": sod["fixed"]["value"]},
+            "rel_l1_vs_fixed": {"E_rho": rel(sa[:, 0, 0], sf[:, 0, 0]),
+                                "Var_rho": rel(np.sum(sa[:, 0, 1:] ** 2, axis=1),
+                                               np.sum(sf[:, 0, 1:] ** 2, axis=1))}},
+    }
+    if not args.no_cpu:
+        import oracle
+        oracle.build()
+        o = oracle.Oracle(spec, ic_fn=lambda nd: W.ic_nodal(spec, nd))
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            o.step(1)
+            k += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cells * k / dt, "unit": "cell-updates/s",
+                               "cores": oracle.load().orc_threads(), "kind": "oracle",
+                               "sample": "first %d adaptive time steps of the same 2D workload, "
+                                         "%.1f s" % (k, dt)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision"], default="plain",
-                    help="plain: the Sod throughput line (default); batch / serve: the "
-                         "batching and serving forms")
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt"],
+                    default="plain",
+                    help="plain: the Sod throughput line (default); batch / serve / precision / "
+                         "adapt: the batching, serving, precision and adaptive forms")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -279,6 +394,9 @@ def main():
         return
     if args.form == "precision":
         print(json.dumps(precision_form(args)), flush=True)
+        return
+    if args.form == "adapt":
+        print(json.dumps(adapt_form(args)), flush=True)
         return
 
     import torch

@@ -177,7 +177,9 @@ ipm_status ipm_set_problem(ipm_ctx *ctx, const ipm_problem *pb, int *problem_id)
    kernel shape (all problems' cells of that shape) and one batched update
    launch per shape, replayed from two device graphs (one per step parity)
    that are built on the first call for this id list and reused while the
-   list and the problems' step counts match.  The results are those of
+   list and the problems' step counts match.  A single problem whose cells
+   span several Newton kernel shapes (per-cell or adaptive degrees) steps the
+   same way, so that its Newton launches overlap.  The results are those of
    stepping each problem alone.  ids must be distinct (IPM_E_ARG).  If info is
    not NULL the call waits and fills info[k] for ids[k]. */
 ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,

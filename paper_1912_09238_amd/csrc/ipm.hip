@@ -1371,7 +1371,15 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
   for (int k = 0; k < n_ids; ++k)
     if (!get(ctx, ids[k])) return fail(ctx, IPM_E_STATE, "ipm_step: unknown problem id");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  if (n_ids >= 2 && max_steps > 0) {
+  // one problem whose cells span several Newton kernel shapes also steps
+  // through a graph, so that those launches overlap instead of queueing
+  bool graph_one = false;
+  if (n_ids == 1 && max_steps > 0) {
+    int shapes = 0;
+    for (const DualClass& D : get(ctx, ids[0])->cls) shapes += D.count > 0 ? 1 : 0;
+    graph_one = shapes >= 2;
+  }
+  if ((n_ids >= 2 || graph_one) && max_steps > 0) {
     // several problems: batched launches per kernel shape, replayed as graphs
     std::vector<int> v(ids, ids + n_ids);
     for (size_t a = 0; a < v.size(); ++a)
