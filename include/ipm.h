@@ -111,11 +111,22 @@ typedef struct {
      the new level (zero-padded when it rises).  The levels start at
      cell_degree (NULL: degree).  Needs min_degree >= 1, delta_lo <= delta_hi
      and quad_per_dim >= degree + 1 (the indicator's averages are then exact
-     sums of squared modes); the classical mode only (one_shot = 0).
+     sums of squared modes).  With one_shot = 1 this is the adaptive one-shot
+     of Alg. adosIPM (one Newton step per cell and pseudo-time step).
      adapt = 0: the per-cell degrees stay fixed and these fields are ignored. */
   int adapt;
   int min_degree;
   double delta_lo, delta_hi;
+  /* Refinement retardation (Sec. 5, Alg. adosIPM), for adapt = 1 and
+     steady_eps > 0: stage l caps every level at retard_degree[l] (a cell
+     takes the smaller of the indicator's level and the cap); the stage
+     advances when the steady residual eq:residualSteady of a step falls to
+     retard_eps[l]; the steady stop applies only in the last stage (whose
+     tolerance is unused).  1..16 stages, degrees non-decreasing within
+     [min_degree, degree]; the arrays are copied.  n_retard = 0: no cap. */
+  int n_retard;
+  const int *retard_degree;
+  const double *retard_eps;
 } ipm_problem;
 
 typedef struct {
@@ -128,6 +139,7 @@ typedef struct {
   long long newton_iters;   /* Newton updates summed over cells and steps */
   long long cell_updates;   /* cells x completed steps */
   int max_iters;            /* largest Newton count of one cell in one step */
+  int retard_stage;         /* current refinement-retardation stage (0 if none) */
 } ipm_step_info;
 
 /* One request of the serving loop (ipm_serve). */

@@ -37,6 +37,11 @@
  *     one quadrature rule serves every level (its nodes contain those of
  *     every coarser level trivially), so a neighbour's ansatz is read at
  *     the shared nodes whatever its level.
+ *   - Refinement retardation (Alg. adosIPM): the printed cap takes the max of
+ *     the determined level and the stage's level; the text calls the stage's
+ *     level the maximal one, so the level is the min of the two.  The stage
+ *     test follows the steady stop test of the same step; the steady stop
+ *     applies only in the last stage.
  */
 #include "ipm_oracle.h"
 
@@ -824,10 +829,15 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
       }
       scratch_free(&w);
     }
-    /* Alg. ad-IPM: the level of the next step from the new dual state */
+    /* Alg. ad-IPM: the level of the next step from the new dual state;
+       Alg. adosIPM: capped by the maximal level of the retardation stage */
     if (S->pb.adapt) {
+      int cap = S->pb.n_retard > 0 ? S->pb.retard_degree[S->info.retard_stage] : S->pb.degree;
 #pragma omp parallel for schedule(static)
-      for (int c = 0; c < S->cells; ++c) S->deg_next[c] = next_level(S, c);
+      for (int c = 0; c < S->cells; ++c) {
+        int dn = next_level(S, c);
+        S->deg_next[c] = dn < cap ? dn : cap;
+      }
     }
     /* time step from the largest wave speed over all cells and nodes */
     double ax = 0.0, ay = 0.0;
@@ -915,8 +925,14 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
     S->info.cell_updates += S->cells;
     if (maxit > S->info.max_iters) S->info.max_iters = maxit;
     S->info.status |= st;
-    if (last || (S->pb.steady_eps > 0.0 && res <= S->pb.steady_eps) || S->info.status)
+    /* steady stop (eq:residualSteady); with retardation only in the last
+       stage, and otherwise the stage advances at its tolerance */
+    int final_stage = S->pb.n_retard == 0 || S->info.retard_stage == S->pb.n_retard - 1;
+    if (last || (S->pb.steady_eps > 0.0 && final_stage && res <= S->pb.steady_eps) ||
+        S->info.status)
       S->info.done = 1;
+    else if (!final_stage && res <= S->pb.retard_eps[S->info.retard_stage])
+      S->info.retard_stage += 1;
   }
   if (info) *info = S->info;
   return S->info.status;

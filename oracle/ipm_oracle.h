@@ -29,6 +29,7 @@ extern "C" {
 #endif
 
 #define ORC_MAXM 4
+#define ORC_MAX_RETARD 16
 
 enum { ORC_BURGERS_1D = 0, ORC_EULER_1D = 1, ORC_EULER_2D = 2 };
 enum { ORC_ENT_QUADRATIC = 0, ORC_ENT_LOG_BARRIER = 1, ORC_ENT_EULER = 2 };
@@ -65,12 +66,20 @@ typedef struct {
      the dual drops the modes above it.  adapt = 0: levels stay fixed. */
   int adapt, min_degree;
   double delta_lo, delta_hi;
+  /* refinement retardation (Sec. 5, Alg. adosIPM), steady runs with
+     adaptivity: stage l caps every level at retard_degree[l]; the stage
+     advances when the steady residual falls to retard_eps[l]; the run stops
+     at steady_eps only in the last stage.  n_retard = 0: no cap. */
+  int n_retard;
+  int retard_degree[ORC_MAX_RETARD];
+  double retard_eps[ORC_MAX_RETARD];
 } orc_problem;
 
 typedef struct {
   double t, dt, residual, amax;
   long long steps, newton_iters, cell_updates;
   int max_iters, status, done;
+  int retard_stage;      /* current stage of the refinement retardation */
 } orc_info;
 
 typedef struct orc_state orc_state;

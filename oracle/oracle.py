@@ -35,6 +35,7 @@ class Problem(C.Structure):
         ("max_newton", C.c_int), ("one_shot", C.c_int),
         ("adapt", C.c_int), ("min_degree", C.c_int),
         ("delta_lo", C.c_double), ("delta_hi", C.c_double),
+        ("n_retard", C.c_int), ("retard_degree", C.c_int * 16), ("retard_eps", C.c_double * 16),
     ]
 
 
@@ -43,6 +44,7 @@ class Info(C.Structure):
         ("t", C.c_double), ("dt", C.c_double), ("residual", C.c_double), ("amax", C.c_double),
         ("steps", C.c_longlong), ("newton_iters", C.c_longlong), ("cell_updates", C.c_longlong),
         ("max_iters", C.c_int), ("status", C.c_int), ("done", C.c_int),
+        ("retard_stage", C.c_int),
     ]
 
     def as_dict(self):
@@ -214,6 +216,11 @@ def make_problem(spec):
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)
     pb.delta_hi = spec.get("delta_hi", 0.0)
+    stages = spec.get("retard", ())  # [(max degree, residual tolerance), ...]
+    pb.n_retard = len(stages)
+    for k, (dg, eps) in enumerate(stages):
+        pb.retard_degree[k] = dg
+        pb.retard_eps[k] = eps
     return pb
 
 

@@ -47,6 +47,8 @@ class Problem(C.Structure):
         ("ic_dual", C.POINTER(C.c_double)), ("dirichlet", C.POINTER(C.c_double)),
         ("adapt", C.c_int), ("min_degree", C.c_int),
         ("delta_lo", C.c_double), ("delta_hi", C.c_double),
+        ("n_retard", C.c_int), ("retard_degree", C.POINTER(C.c_int)),
+        ("retard_eps", C.POINTER(C.c_double)),
     ]
 
 
@@ -54,7 +56,8 @@ class StepInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("done", C.c_int), ("steps", C.c_longlong),
                 ("t", C.c_double), ("dt", C.c_double), ("residual", C.c_double),
                 ("amax", C.c_double), ("newton_iters", C.c_longlong),
-                ("cell_updates", C.c_longlong), ("max_iters", C.c_int)]
+                ("cell_updates", C.c_longlong), ("max_iters", C.c_int),
+                ("retard_stage", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -173,6 +176,14 @@ def problem_struct(spec, keep):
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)
     pb.delta_hi = spec.get("delta_hi", 0.0)
+    stages = spec.get("retard", ())  # [(max degree, residual tolerance), ...]
+    pb.n_retard = len(stages)
+    if stages:
+        dg = (C.c_int * len(stages))(*[int(d) for d, _ in stages])
+        ep = (C.c_double * len(stages))(*[float(e) for _, e in stages])
+        keep.extend([dg, ep])
+        pb.retard_degree = C.cast(dg, C.POINTER(C.c_int))
+        pb.retard_eps = C.cast(ep, C.POINTER(C.c_double))
     pb.nx = spec["nx"]
     pb.ny = spec.get("ny", 1)
     pb.x0, pb.x1 = spec["x0"], spec["x1"]

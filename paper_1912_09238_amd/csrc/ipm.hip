@@ -61,6 +61,10 @@ struct Problem {
   // dynamic adaptivity: levels move between min_degree and degree
   int adapt = 0, min_degree = 1;
   double delta_lo = 0.0, delta_hi = 0.0;
+  Retard* d_retard = nullptr;  // refinement retardation state (null: none)
+  // Newton launches run over the step's work lists (else over all cells of
+  // each class in a fixed order: one-shot with fixed degrees)
+  bool lists() const { return !one_shot || adapt; }
   double* d_phi = nullptr;
   double* d_wphi = nullptr;
   double* d_u[2] = {nullptr, nullptr};
@@ -332,7 +336,7 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
@@ -551,6 +555,7 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.delta_hi = P.delta_hi;
   u.cellN_next = P.adapt ? P.d_cellN[parity ^ 1] : nullptr;
   u.lam = P.d_lam;
+  u.retard = P.d_retard;
   return u;
 }
 
@@ -572,7 +577,7 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
     ctx->ev_used += 4;
     HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
   }
-  ipm_status st = launch_dual_classes(ctx, P, d, !P.one_shot);
+  ipm_status st = launch_dual_classes(ctx, P, d, P.lists());
   if (st != IPM_OK) return st;
   if (ctx->timing) {
     HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
@@ -585,7 +590,7 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   if (ctx->timing) HIPCHK(ctx, hipEventRecord(e3, ctx->stream));
   if (P.steady_eps > 0.0) {
     hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
-                       P.upd_blocks, P.steady_eps, parity, P.d_blk, P.dual_blocks, 0);
+                       P.upd_blocks, P.steady_eps, parity, P.d_blk, P.dual_blocks, 0, P.d_retard);
     HIPCHK(ctx, hipGetLastError());
   }
   ++P.step_index;
@@ -596,7 +601,7 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
 ipm_status enqueue_close(ipm_ctx* ctx, Problem& P) {
   hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
                      P.upd_blocks, P.steady_eps, static_cast<int>(P.step_index & 1), P.d_blk,
-                     P.dual_blocks, 1);
+                     P.dual_blocks, 1, P.d_retard);
   HIPCHK(ctx, hipGetLastError());
   return IPM_OK;
 }
@@ -702,7 +707,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         first = false;
         dc.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
         int items;
-        if (!P.one_shot) {
+        if (P.lists()) {
           dc.lists = D.d_lists + static_cast<size_t>(parity) * kSlots * D.cap;
           dc.list_cap = D.cap;
           items = kSlots * D.cap;
@@ -838,7 +843,8 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         int par = L.parity;
         const unsigned long long* bs = P.d_blk;
         int nblk = P.dual_blocks, close = 0;
-        void* args[8] = {&C, &rp, &nparts, &eps, &par, &bs, &nblk, &close};
+        Retard* R = P.d_retard;
+        void* args[9] = {&C, &rp, &nparts, &eps, &par, &bs, &nblk, &close, &R};
         kp.func = reinterpret_cast<void*>(residual_kernel);
         kp.gridDim = dim3(1);
         kp.blockDim = dim3(256);
@@ -900,7 +906,8 @@ ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
         } else {
           const Problem& P = *get(ctx, L.pid);
           hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
-                             P.upd_blocks, P.steady_eps, L.parity, P.d_blk, P.dual_blocks, 0);
+                             P.upd_blocks, P.steady_eps, L.parity, P.d_blk, P.dual_blocks, 0,
+                             P.d_retard);
           HIPCHK(ctx, hipGetLastError());
         }
       }
@@ -997,7 +1004,17 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
       return fail(ctx, IPM_E_ARG, "adaptivity needs delta_lo <= delta_hi");
     if (pb->quad_per_dim < pb->degree + 1)
       return fail(ctx, IPM_E_ARG, "adaptivity needs quad_per_dim >= degree + 1");
-    if (pb->one_shot) return fail(ctx, IPM_E_ARG, "adaptivity runs in the classical mode (one_shot = 0)");
+  }
+  if (pb->n_retard != 0) {
+    if (!pb->adapt || !(pb->steady_eps > 0.0))
+      return fail(ctx, IPM_E_ARG, "refinement retardation needs adapt = 1 and steady_eps > 0");
+    if (pb->n_retard < 0 || pb->n_retard > kMaxRetard || !pb->retard_degree || !pb->retard_eps)
+      return fail(ctx, IPM_E_ARG, "refinement retardation needs 1..16 stages with degrees and tolerances");
+    for (int k = 0; k < pb->n_retard; ++k) {
+      const int dg = pb->retard_degree[k];
+      if (dg < pb->min_degree || dg > pb->degree || (k > 0 && dg < pb->retard_degree[k - 1]))
+        return fail(ctx, IPM_E_ARG, "retardation degrees must be non-decreasing in [min_degree, degree]");
+    }
   }
   return IPM_OK;
 }
@@ -1214,6 +1231,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     if (P.uneven && D.order_len > 0) ALLOC(D.d_order, static_cast<size_t>(D.order_len) * sizeof(int));
   }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
+  if (pb->n_retard > 0) ALLOC(P.d_retard, sizeof(Retard));
   if (P.uneven) ALLOC(P.d_cellN[0], static_cast<size_t>(P.cells));
   if (P.adapt) ALLOC(P.d_cellN[1], static_cast<size_t>(P.cells));
   else P.d_cellN[1] = P.d_cellN[0];
@@ -1239,6 +1257,41 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
                            hipMemcpyHostToDevice, s));
   }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  Retard hr{};
+  if (P.d_retard) {
+    hr.n = pb->n_retard;
+    for (int k = 0; k < hr.n; ++k) {
+      hr.deg[k] = pb->retard_degree[k];
+      hr.eps[k] = pb->retard_eps[k];
+    }
+    CHK(hipMemcpyAsync(P.d_retard, &hr, sizeof(Retard), hipMemcpyHostToDevice, s));
+  }
+  // one-shot over work lists (adaptive): the first step's lists hold every
+  // cell, by its initial size class, spread over the slots
+  std::vector<std::vector<int>> first_lists(kCls);
+  std::vector<unsigned> first_len(static_cast<size_t>(kCls) * kSlots, 0u);
+  if (P.one_shot && P.lists()) {
+    for (int c = 0; c < P.cells; ++c) {
+      const int k = cell_cls[c];
+      const DualClass& D = P.cls[k];
+      std::vector<int>& L = first_lists[k];
+      if (L.empty()) L.assign(static_cast<size_t>(kSlots) * D.cap, -1);
+      const int slot = (c / std::max(1, (P.cells + kSlots - 1) / kSlots)) % kSlots;
+      unsigned& len = first_len[static_cast<size_t>(k) * kSlots + slot];
+      if (static_cast<int>(len) >= D.cap) return cleanup(fail(ctx, IPM_E_ARG, "work list overflow"));
+      L[static_cast<size_t>(slot) * D.cap + len++] = c;
+    }
+    for (int k = 0; k < kCls; ++k)
+      if (!first_lists[k].empty())
+        CHK(hipMemcpyAsync(P.cls[k].d_lists, first_lists[k].data(),
+                           first_lists[k].size() * sizeof(int), hipMemcpyHostToDevice, s));
+    std::vector<unsigned> lens(sizeof(StepCtrl::list_len) / sizeof(unsigned), 0u);
+    for (int k = 0; k < kCls; ++k)
+      for (int sl = 0; sl < kSlots; ++sl)
+        lens[list_len_index(0, k, sl)] = first_len[static_cast<size_t>(k) * kSlots + sl];
+    CHK(hipMemcpyAsync(&P.d_ctrl->list_len[0], lens.data(), lens.size() * sizeof(unsigned),
+                       hipMemcpyHostToDevice, s));
+  }
   CHK(hipMemsetAsync(P.d_blk, 0, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long), s));
   CHK(hipMemsetAsync(P.d_res, 0, static_cast<size_t>(P.upd_blocks) * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_ghost, 0, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double), s));
@@ -1430,6 +1483,13 @@ ipm_status ipm_query(ipm_ctx* ctx, int id, ipm_step_info* info) {
   info->newton_iters = static_cast<long long>(hc.newton_iters);
   info->cell_updates = static_cast<long long>(hc.steps) * P->cells;
   info->max_iters = static_cast<int>(hc.max_iters);
+  info->retard_stage = 0;
+  if (P->d_retard) {
+    Retard hr;
+    HIPCHK(ctx, hipMemcpyAsync(&hr, P->d_retard, sizeof(Retard), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    info->retard_stage = hr.stage;
+  }
   const unsigned st = hc.status;
   info->status = st == 0u                  ? IPM_OK
                  : (st & kStNonfinite)     ? IPM_E_NONFINITE

@@ -32,6 +32,16 @@
 
 namespace ipm {
 
+// Refinement retardation (Sec. 5, Alg. adosIPM): stage l caps the levels at
+// deg[l]; the residual kernel advances the stage when the steady residual
+// reaches eps[l].  One per problem in device memory.
+constexpr int kMaxRetard = 16;
+struct Retard {
+  int n, stage;
+  int deg[kMaxRetard];
+  double eps[kMaxRetard];
+};
+
 struct UpdateParams {
   const double* __restrict__ wphi;   // [Q][kp]
   int N, Q, kp, cells, nx, ny, dim;
@@ -56,6 +66,7 @@ struct UpdateParams {
   double delta_lo, delta_hi;
   int8_t* __restrict__ cellN_next;   // [cells] modes of the next step
   double* __restrict__ lam;          // [cells][M][N]
+  const Retard* retard;              // null: no level cap
 };
 
 // number of basis functions of total degree <= d in p dimensions,
@@ -242,6 +253,7 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
       int dn = d;
       if (ind < P.delta_lo && d > P.deg_min) dn = d - 1;
       else if (ind > P.delta_hi && d < P.deg_max) dn = d + 1;
+      if (P.retard) dn = min(dn, P.retard->deg[P.retard->stage]);  // Alg. adosIPM cap
       Nn = basis_count(P.p, dn);
       if (r == 0) P.cellN_next[cell] = static_cast<int8_t>(Nn);
       if (Nn < Nc) {
@@ -281,6 +293,8 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
       for (int b = 0; b < M; ++b) resn += sqrt(group_sum<G>(gsq[b]));
       // NaN routes to Newton, which reports it; the value is the list class + 1
       route = (resn < 0.5 * P.tau && !lowered) ? 0 : 1 + size_class(Nn * M);
+    } else if (P.adapt) {
+      route = 1 + size_class(Nn * M);  // one-shot: every cell, at its new level
     }
   }
   // speeds of the cells whose nodal ansatz carries over to the next step
@@ -323,7 +337,7 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         if (P.dim == 2) atomicMax(&C->amax[P.parity ^ 1][1][slot * kSlotStride], speed_bits(my));
       }
     }
-    if (!P.one_shot)
+    if (!P.one_shot || P.adapt)
       for (int c = 0; c < kCls; ++c) {
         // groups routed to class c, in group order: one atomic per class
         const unsigned long long m = __ballot(rk == c + 1);
@@ -367,7 +381,7 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateParams* __rest
 __global__ __launch_bounds__(256) void residual_kernel(StepCtrl* C, const double* res_part,
                                                        int nparts, double steady_eps, int parity,
                                                        const unsigned long long* blk_stats,
-                                                       int nblk, int close) {
+                                                       int nblk, int close, Retard* R) {
   __shared__ double red[256];
   __shared__ unsigned long long rit[256];
   __shared__ unsigned long long rmx[256];
@@ -394,9 +408,16 @@ __global__ __launch_bounds__(256) void residual_kernel(StepCtrl* C, const double
   }
   if (threadIdx.x == 0) {
     if (C->steps > 0) C->residual = red[0];
-    if (!close && !C->done[parity] && !C->status && steady_eps > 0.0 && C->steps > 0 &&
-        red[0] <= steady_eps)
-      C->done[parity ^ 1] = 1;
+    // steady stop; with refinement retardation only in the last stage, and
+    // before it the stage advances at its own tolerance
+    if (!close && !C->done[parity] && !C->status && steady_eps > 0.0 && C->steps > 0) {
+      const bool final_stage = !R || R->stage >= R->n - 1;
+      if (final_stage) {
+        if (red[0] <= steady_eps) C->done[parity ^ 1] = 1;
+      } else if (!C->done[parity ^ 1] && red[0] <= R->eps[R->stage]) {
+        R->stage += 1;
+      }
+    }
     if (close) {
       C->newton_iters = rit[0];
       C->max_iters = static_cast<unsigned>(rmx[0]);
