@@ -354,12 +354,75 @@ def adapt_form(args):
     return out
 
 
+def steady_form(args):
+    """Steady form (Sec. 4 and 5): the steady inflow problem (Burgers,
+    log-barrier entropy, Dirichlet inflow 1 + 0.2 xi, closed-form steady state
+    uhat = (1, 0.2/sqrt(3), 0, ...)) on 2048 cells at degree 9, 10 nodes,
+    iterated to the steady residual 1e-10 by IPM (Alg. IPM), one-shot IPM
+    (Alg. osIPM), adaptive one-shot (Alg. adosIPM, levels 1..9) and adaptive
+    one-shot with refinement retardation (level cap 1 until the residual
+    reaches 3e-3); time to the steady state and distance to the closed form."""
+    import torch
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    base = W.steady_inflow(nx=args.steady_nx, degree=9, qpd=10, eps=1e-10)
+    nodes, _ = binding.quadrature(1, 10)
+    ic, dn = W.ic_nodal(base, nodes), W.dirichlet_nodal(base, nodes)
+    ad = dict(adapt=1, min_degree=1, delta_lo=1e-6, delta_hi=5e-2)
+    variants = [("IPM", dict(base)), ("osIPM", dict(base, one_shot=1)),
+                ("adosIPM", dict(base, one_shot=1, **ad)),
+                ("readosIPM", dict(base, one_shot=1, retard=((1, 3e-3), (9, 0.0)), **ad))]
+    want = np.zeros(10)
+    want[0], want[1] = 1.0, 0.2 / np.sqrt(3.0)
+    warm = ctx.set_problem(variants[3][1], ic_nodal=ic, dirichlet=dn)
+    ctx.step(warm, 20, wait=True)
+    ctx.release(warm)
+    res = {}
+    for name, sp in variants:
+        pid = ctx.set_problem(sp, ic_nodal=ic, dirichlet=dn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            ctx.step(pid, 512)
+            info = ctx.query(pid)
+            if info["done"] or info["steps"] >= 200000:
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert info["status"] == 0 and info["done"], (name, info)
+        mom = ctx.moments(pid)
+        lv = np.bincount(ctx.degrees(pid), minlength=10)
+        ctx.release(pid)
+        res[name] = {"seconds": el, "steps": info["steps"], "newton_iters": info["newton_iters"],
+                     "value": base["nx"] * info["steps"] / el,
+                     "max_err_vs_closed_form": float(np.max(np.abs(mom[:, 0, :] - want))),
+                     "final_levels": {str(k): int(v) for k, v in enumerate(lv) if v}}
+        print("steady form: %s %d steps %.3f s" % (name, info["steps"], el), file=sys.stderr,
+              flush=True)
+    ctx.close()
+    r = res["readosIPM"]
+    return {
+        "metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": r["steps"], "warmup": 20, "ms_per_step": r["seconds"] / r["steps"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "steady_inflow_burgers_nx%d_deg9_q10_logbarrier_fp64" % args.steady_nx,
+                   "cells": args.steady_nx, "steady_eps": 1e-10, "parallelism": "single-gpu"},
+        "time_to_steady_s": {k: v["seconds"] for k, v in res.items()},
+        "speedup_vs_IPM": {k: res["IPM"]["seconds"] / v["seconds"] for k, v in res.items()},
+        "variants": res,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt"],
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt", "steady"],
                     default="plain",
                     help="plain: the Sod throughput line (default); batch / serve / precision / "
-                         "adapt: the batching, serving, precision and adaptive forms")
+                         "adapt / steady: the batching, serving, precision, adaptive and "
+                         "steady (one-shot, retardation) forms")
+    ap.add_argument("--steady-nx", type=int, default=2048)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -397,6 +460,9 @@ def main():
         return
     if args.form == "adapt":
         print(json.dumps(adapt_form(args)), flush=True)
+        return
+    if args.form == "steady":
+        print(json.dumps(steady_form(args)), flush=True)
         return
 
     import torch
