@@ -45,7 +45,12 @@ struct DualClass {
   int* d_lists = nullptr;   // [2][64][cap] Newton lists by step parity
   int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
   int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
+  bool merged = false;      // its cells go to the lists of a larger class
 };
+
+// Problems up to this many cells are latency bound: one Newton launch for
+// two adjacent small-cell classes beats one launch each.
+constexpr int kMergeCells = 32768;
 
 struct Problem {
   int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, UG = 16;
@@ -62,6 +67,7 @@ struct Problem {
   int adapt = 0, min_degree = 1;
   double delta_lo = 0.0, delta_hi = 0.0;
   Retard* d_retard = nullptr;  // refinement retardation state (null: none)
+  unsigned cls_map = 0x76543210u;  // 4 bits per size class: the class whose lists take its cells
   // Newton launches run over the step's work lists (else over all cells of
   // each class in a fixed order: one-shot with fixed degrees)
   bool lists() const { return !one_shot || adapt; }
@@ -418,8 +424,30 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     if (D.lds > ctx->max_lds)
       return fail(ctx, IPM_E_ARG, "quadrature too large for the dual kernel's LDS tiles (Q = " +
                                       std::to_string(P.Q) + ")");
+  }
+  // a small problem's cells of the next smaller small-cell class run in the
+  // largest small-cell class's launch (their unknowns fit its lane groups;
+  // the kernel handles cells of any size up to its own)
+  P.cls_map = 0x76543210u;
+  if (P.lists() && P.cells <= kMergeCells) {
+    int top = -1;
+    for (int c = 0; c < 4; ++c)
+      if (P.cls[c].configured && P.cls[c].count > 0 && P.cls[c].T == 0) top = c;
+    if (top > 0) {
+      DualClass& L = P.cls[top - 1];
+      if (L.configured && L.count > 0 && L.T == 0) {
+        L.merged = true;
+        P.cls[top].count = std::min(P.cells, P.cls[top].count + L.count);
+        P.cls_map = (P.cls_map & ~(15u << (4 * (top - 1)))) | (static_cast<unsigned>(top) << (4 * (top - 1)));
+      }
+    }
+  }
+  for (int c = 0; c < kCls; ++c) {
+    DualClass& D = P.cls[c];
+    if (!D.configured) continue;
     // list l receives the routed cells of update blocks b = l (mod 64)
-    D.cap = D.count > 0 ? std::min(((P.upd_blocks + kSlots - 1) / kSlots) * ucpb, D.count) : 0;
+    D.cap = (D.count > 0 && !D.merged)
+                ? std::min(((P.upd_blocks + kSlots - 1) / kSlots) * ucpb, D.count) : 0;
     // block statistics sized for one wavefront per block, the smallest the
     // autotuner may choose
     const int per_block = D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP);
@@ -504,7 +532,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
 ipm_status launch_dual_classes(ipm_ctx* ctx, const Problem& P, const DualParams& d, bool list_mode) {
   bool first = true;
   for (int c = 0; c < kCls; ++c) {
-    if (P.cls[c].count == 0) continue;
+    if (P.cls[c].count == 0 || (list_mode && P.cls[c].merged)) continue;
     DualParams dc = d;
     dc.reset_next = first ? 1 : 0;
     first = false;
@@ -556,6 +584,7 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.cellN_next = P.adapt ? P.d_cellN[parity ^ 1] : nullptr;
   u.lam = P.d_lam;
   u.retard = P.d_retard;
+  u.cls_map = P.cls_map;
   return u;
 }
 
@@ -699,7 +728,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
       bool first = true;
       for (int c = 0; c < kCls; ++c) {
         const DualClass& D = P.cls[c];
-        if (D.count == 0) continue;
+        if (D.count == 0 || (P.lists() && D.merged)) continue;
         DualParams dc = d;
         dc.cls = c;
         dc.bcache = D.bcache;
@@ -1272,7 +1301,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   std::vector<unsigned> first_len(static_cast<size_t>(kCls) * kSlots, 0u);
   if (P.one_shot && P.lists()) {
     for (int c = 0; c < P.cells; ++c) {
-      const int k = cell_cls[c];
+      const int k = static_cast<int>((P.cls_map >> (4 * cell_cls[c])) & 15u);
       const DualClass& D = P.cls[k];
       std::vector<int>& L = first_lists[k];
       if (L.empty()) L.assign(static_cast<size_t>(kSlots) * D.cap, -1);
@@ -1429,7 +1458,7 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
   bool graph_one = false;
   if (n_ids == 1 && max_steps > 0) {
     int shapes = 0;
-    for (const DualClass& D : get(ctx, ids[0])->cls) shapes += D.count > 0 ? 1 : 0;
+    for (const DualClass& D : get(ctx, ids[0])->cls) shapes += (D.count > 0 && !D.merged) ? 1 : 0;
     graph_one = shapes >= 2;
   }
   if ((n_ids >= 2 || graph_one) && max_steps > 0) {
@@ -1711,7 +1740,8 @@ ipm_status ipm_autotune(ipm_ctx* ctx, int n_ids, const int* ids, int steps_per_c
   for (int k = 0; k < n_ids; ++k) {
     Problem* P = get(ctx, ids[k]);
     for (int c = 0; c < kCls; ++c)
-      if (P->cls[c].count > 0 && P->cls[c].T == 0) shapes[tune_key(*P, P->cls[c])].push_back({P, c});
+      if (P->cls[c].count > 0 && P->cls[c].T == 0 && !P->cls[c].merged)
+        shapes[tune_key(*P, P->cls[c])].push_back({P, c});
   }
   hipEvent_t e0, e1;
   HIPCHK(ctx, hipEventCreate(&e0));

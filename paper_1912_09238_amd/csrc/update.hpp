@@ -67,6 +67,7 @@ struct UpdateParams {
   int8_t* __restrict__ cellN_next;   // [cells] modes of the next step
   double* __restrict__ lam;          // [cells][M][N]
   const Retard* retard;              // null: no level cap
+  unsigned cls_map;                  // 4 bits per size class: the class whose lists take its cells
 };
 
 // number of basis functions of total degree <= d in p dimensions,
@@ -292,9 +293,10 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
 #pragma unroll
       for (int b = 0; b < M; ++b) resn += sqrt(group_sum<G>(gsq[b]));
       // NaN routes to Newton, which reports it; the value is the list class + 1
-      route = (resn < 0.5 * P.tau && !lowered) ? 0 : 1 + size_class(Nn * M);
-    } else if (P.adapt) {
-      route = 1 + size_class(Nn * M);  // one-shot: every cell, at its new level
+      route = (resn < 0.5 * P.tau && !lowered)
+                  ? 0 : 1 + static_cast<int>((P.cls_map >> (4 * size_class(Nn * M))) & 15u);
+    } else if (P.adapt) {  // one-shot: every cell, at its new level
+      route = 1 + static_cast<int>((P.cls_map >> (4 * size_class(Nn * M))) & 15u);
     }
   }
   // speeds of the cells whose nodal ansatz carries over to the next step
