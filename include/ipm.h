@@ -64,8 +64,17 @@ enum { IPM_BURGERS_1D = 0, IPM_EULER_1D = 1, IPM_EULER_2D = 2 };
    Galerkin; log-barrier (u-u_-)ln(u-u_-)+(u_+-u)ln(u_+-u) for scalar
    problems; the Euler entropy -rho ln(rho^-gamma (E-|m|^2/(2 rho))) of App. B */
 enum { IPM_ENT_QUADRATIC = 0, IPM_ENT_LOG_BARRIER = 1, IPM_ENT_EULER = 2 };
-/* deterministic numerical flux g of the kinetic flux eq:numericalFluxIPM */
-enum { IPM_FLUX_LF = 0, IPM_FLUX_RUSANOV = 1 };
+/* With the quadratic entropy the Euler equations' ansatz is the SG
+   expansion; a node with non-positive density or pressure is reported as
+   IPM_E_REALIZABILITY (the failure of stochastic Galerkin, Sec. 7). */
+/* deterministic numerical flux g of the kinetic flux eq:numericalFluxIPM;
+   IPM_FLUX_SG_ANALYTIC: the Lax-Friedrichs flux of the stochastic-Galerkin
+   moment system of Burgers' equation with the triple products
+   <phi_a phi_b phi_i> (App. A, eq:numFluxAnalytic), O(N^3) per face instead
+   of O(N Q); Burgers with the quadratic entropy, outflow or periodic
+   boundaries, fixed degrees, N <= 16.  It equals the LF kinetic flux when
+   the rule integrates degree 3M exactly. */
+enum { IPM_FLUX_LF = 0, IPM_FLUX_RUSANOV = 1, IPM_FLUX_SG_ANALYTIC = 2 };
 enum { IPM_BC_OUTFLOW = 0, IPM_BC_PERIODIC = 1, IPM_BC_DIRICHLET = 2 };
 /* arithmetic of the Hessian assembly (Newton update, Cholesky solve, gradient
    and the tau test are always FP64) */

@@ -259,6 +259,15 @@ int orc_closure(int entropy, int m, double gamma, double um, double up,
       for (int b = 0; b < m; ++b) J[a * m + b] = (a == b) ? 1.0 : 0.0;
     }
     *sstar = s;
+    /* gas dynamics: a stochastic-Galerkin state with a non-positive density
+       or pressure at a node has no physical flux (the failure of SG noted in
+       Sec. 7); it is reported as inadmissible */
+    if (m >= 3) {
+      double mm = 0.0;
+      for (int k = 1; k < m - 1; ++k) mm += u[k] * u[k];
+      if (!(u[0] > 0.0)) return 0;
+      if (!((gamma - 1.0) * (u[m - 1] - 0.5 * mm / u[0]) > 0.0)) return 0;
+    }
     return 1;
   }
   if (entropy == ORC_ENT_LOG_BARRIER) {
@@ -419,6 +428,7 @@ struct orc_state {
   int *deg, *deg_next;     /* total degree per cell: this step, next step */
   double *uhat, *lam, *unew, *nodal; /* [cells][m][N] x3, [cells][Q][m] */
   double *ghost[4];        /* Dirichlet ghost nodal states [Q][m] */
+  double *Ctp;             /* [N][N][N] <phi_i phi_n phi_k> (analytic SG flux) */
   int *iters;
   orc_info info;
 };
@@ -684,6 +694,29 @@ orc_state *orc_create(const orc_problem *pb, const signed char *cell_degree,
   S->Phi = (double *)malloc(sizeof(double) * Q * S->N);
   orc_quadrature(pb->p, pb->quad_per_dim, S->nodes, S->w);
   orc_basis_eval(pb->p, pb->degree, Q, S->nodes, S->Phi);
+  if (pb->flux == ORC_FLUX_SG_ANALYTIC) {
+    /* App. A: C_i = <phi phi^T phi_i>, integrands of degree <= 3M, by a
+       tensor Gauss-Legendre rule exact to that degree */
+    int qc = (3 * pb->degree) / 2 + 1, Qc = 1;
+    for (int k = 0; k < pb->p; ++k) Qc *= qc;
+    double *nc = (double *)malloc(sizeof(double) * Qc * pb->p);
+    double *wc = (double *)malloc(sizeof(double) * Qc);
+    double *Pc = (double *)malloc(sizeof(double) * Qc * S->N);
+    orc_quadrature(pb->p, qc, nc, wc);
+    orc_basis_eval(pb->p, pb->degree, Qc, nc, Pc);
+    int N = S->N;
+    S->Ctp = (double *)calloc((size_t)N * N * N, sizeof(double));
+    for (int i = 0; i < N; ++i)
+      for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+          double t = 0.0;
+          for (int q = 0; q < Qc; ++q) t += wc[q] * Pc[q * N + i] * Pc[q * N + a] * Pc[q * N + b];
+          S->Ctp[((size_t)i * N + a) * N + b] = t;
+        }
+    free(nc);
+    free(wc);
+    free(Pc);
+  }
   size_t cn = (size_t)S->cells * S->n;
   S->uhat = (double *)calloc(cn, sizeof(double));
   S->lam = (double *)calloc(cn, sizeof(double));
@@ -742,7 +775,7 @@ void orc_destroy(orc_state *S)
 {
   if (!S) return;
   free(S->nodes); free(S->w); free(S->Phi); free(S->uhat); free(S->lam); free(S->unew);
-  free(S->nodal); free(S->iters); free(S->Nc); free(S->deg); free(S->deg_next);
+  free(S->nodal); free(S->iters); free(S->Nc); free(S->deg); free(S->deg_next); free(S->Ctp);
   for (int k = 0; k < 4; ++k) free(S->ghost[k]);
   free(S);
 }
@@ -868,6 +901,32 @@ int orc_step(orc_state *S, int max_steps, orc_info *info)
        in the quadrature form eq:momentUpQuadrature */
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < S->cells; ++c) {
+      if (S->pb.flux == ORC_FLUX_SG_ANALYTIC) {
+        /* App. A, eq:numFluxAnalytic on the duals of the cell and its two
+           neighbours (outflow: the cell itself, periodic: wrap) */
+        int N = S->N, nx = S->pb.nx;
+        int cw = c - 1, ce = c + 1;
+        if (cw < 0) cw = S->pb.bc[0] == ORC_BC_PERIODIC ? nx - 1 : c;
+        if (ce >= nx) ce = S->pb.bc[1] == ORC_BC_PERIODIC ? 0 : c;
+        const double *lw = S->lam + (size_t)cw * n, *lc = S->lam + (size_t)c * n,
+                     *le = S->lam + (size_t)ce * n;
+        int Nn = S->pb.adapt ? orc_num_basis(S->pb.p, S->deg_next[c]) : S->Nc[c];
+        double visc = S->dx / (2.0 * dt);
+        for (int i = 0; i < N; ++i) {
+          double Fw = 0.0, Fc = 0.0, Fe = 0.0;
+          for (int a = 0; a < N; ++a)
+            for (int b = 0; b < N; ++b) {
+              double C = S->Ctp[((size_t)i * N + a) * N + b];
+              Fw += 0.5 * C * lw[a] * lw[b];
+              Fc += 0.5 * C * lc[a] * lc[b];
+              Fe += 0.5 * C * le[a] * le[b];
+            }
+          double Gr = 0.5 * (Fc + Fe) - visc * (le[i] - lc[i]);
+          double Gl = 0.5 * (Fw + Fc) - visc * (lc[i] - lw[i]);
+          S->unew[(size_t)c * n + i] = i < Nn ? lc[i] - dt / S->dx * (Gr - Gl) : 0.0;
+        }
+        continue;
+      }
       int ix = c % S->pb.nx, iy = c / S->pb.nx;
       const double *uc = S->nodal + (size_t)c * Q * m;
       const double *uw = neighbour(S, ix, iy, 0), *ue = neighbour(S, ix, iy, 1);

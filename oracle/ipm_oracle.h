@@ -33,7 +33,11 @@ extern "C" {
 
 enum { ORC_BURGERS_1D = 0, ORC_EULER_1D = 1, ORC_EULER_2D = 2 };
 enum { ORC_ENT_QUADRATIC = 0, ORC_ENT_LOG_BARRIER = 1, ORC_ENT_EULER = 2 };
-enum { ORC_FLUX_LF = 0, ORC_FLUX_RUSANOV = 1 };
+/* ORC_FLUX_SG_ANALYTIC: App. A, eq:numFluxAnalytic -- the Lax-Friedrichs flux
+   of the stochastic-Galerkin moment system of Burgers' equation with the
+   triple products <phi_n phi_k phi_i>, applied to the duals (quadratic
+   entropy: the dual is the SG moment vector); 1D Burgers only */
+enum { ORC_FLUX_LF = 0, ORC_FLUX_RUSANOV = 1, ORC_FLUX_SG_ANALYTIC = 2 };
 enum { ORC_BC_OUTFLOW = 0, ORC_BC_PERIODIC = 1, ORC_BC_DIRICHLET = 2 };
 
 /* status bits, sticky per problem */

@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "ipm_oracle.c")
 
 EQ = {"burgers1d": 0, "euler1d": 1, "euler2d": 2}
 ENT = {"quadratic": 0, "log_barrier": 1, "euler": 2}
-FLUX = {"lf": 0, "rusanov": 1}
+FLUX = {"lf": 0, "rusanov": 1, "sg_analytic": 2}
 BC = {"outflow": 0, "periodic": 1, "dirichlet": 2}
 STATUS = {"newton": 1, "realizability": 2, "nonfinite": 4, "cholesky": 8, "linesearch": 16}
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libipm.so")
 
 EQ = {"burgers1d": 0, "euler1d": 1, "euler2d": 2}
 ENT = {"quadratic": 0, "log_barrier": 1, "euler": 2}
-FLUX = {"lf": 0, "rusanov": 1}
+FLUX = {"lf": 0, "rusanov": 1, "sg_analytic": 2}
 BC = {"outflow": 0, "periodic": 1, "dirichlet": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 STATUS = {0: "ok", -1: "arg", -2: "state", -3: "nomem", -4: "realizability", -5: "newton",

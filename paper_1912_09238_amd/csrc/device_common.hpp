@@ -12,7 +12,8 @@ namespace ipm {
 
 enum { kBurgers1D = 0, kEuler1D = 1, kEuler2D = 2 };
 enum { kEntQuadratic = 0, kEntLogBarrier = 1, kEntEuler = 2 };
-enum { kFluxLF = 0, kFluxRusanov = 1 };
+// kFluxSgAnalytic: App. A, eq:numFluxAnalytic (Burgers, quadratic entropy)
+enum { kFluxLF = 0, kFluxRusanov = 1, kFluxSgAnalytic = 2 };
 enum { kBcOutflow = 0, kBcPeriodic = 1, kBcDirichlet = 2 };
 
 // status bits kept per problem on the device
@@ -63,6 +64,15 @@ __device__ __forceinline__ bool closure(const ClosureParams& cp, const double* L
 #pragma unroll
       for (int b = a; b < M; ++b) J[Packed<M>::idx(a, b)] = (a == b) ? 1.0 : 0.0;
     sstar = 0.5 * s;
+    if constexpr (M >= 3) {
+      // gas dynamics: a stochastic-Galerkin state with a non-positive
+      // density or pressure at a node has no physical flux (SG's failure)
+      double mm = 0.0;
+#pragma unroll
+      for (int k = 1; k < M - 1; ++k) mm += u[k] * u[k];
+      if (!(u[0] > 0.0)) return false;
+      if (!((cp.gamma - 1.0) * (u[M - 1] - 0.5 * mm / u[0]) > 0.0)) return false;
+    }
     return true;
   }
   if (M == 1 && cp.entropy == kEntLogBarrier) {

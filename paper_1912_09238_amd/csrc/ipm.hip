@@ -82,6 +82,7 @@ struct Problem {
   // modes per cell read by the steps of each parity (one buffer when fixed;
   // adaptive: the update of a step writes the other parity's buffer)
   int8_t* d_cellN[2] = {nullptr, nullptr};
+  double* d_ctp = nullptr;  // analytic SG flux: triple products [N][N][N]
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;    // device bytes allocated
@@ -342,7 +343,7 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
@@ -391,7 +392,8 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   const int ucpb = 4 * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
   P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
-                                2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256);
+                                2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
+                                (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
   if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
   P.dual_blocks = 0;
   for (int c = 0; c < kCls; ++c) {
@@ -585,6 +587,7 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.lam = P.d_lam;
   u.retard = P.d_retard;
   u.cls_map = P.cls_map;
+  u.ctp = P.d_ctp;
   return u;
 }
 
@@ -992,8 +995,17 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
     return fail(ctx, IPM_E_ARG, "Burgers needs the quadratic or the log-barrier entropy");
   if (M > 1 && pb->entropy != IPM_ENT_QUADRATIC && pb->entropy != IPM_ENT_EULER)
     return fail(ctx, IPM_E_ARG, "Euler needs the quadratic or the Euler entropy");
-  if (pb->flux != IPM_FLUX_LF && pb->flux != IPM_FLUX_RUSANOV)
+  if (pb->flux != IPM_FLUX_LF && pb->flux != IPM_FLUX_RUSANOV && pb->flux != IPM_FLUX_SG_ANALYTIC)
     return fail(ctx, IPM_E_ARG, "flux out of range");
+  if (pb->flux == IPM_FLUX_SG_ANALYTIC) {
+    if (pb->equation != IPM_BURGERS_1D || pb->entropy != IPM_ENT_QUADRATIC)
+      return fail(ctx, IPM_E_ARG, "the analytic SG flux needs Burgers with the quadratic entropy");
+    if (pb->bc[0] == IPM_BC_DIRICHLET || pb->bc[1] == IPM_BC_DIRICHLET || pb->adapt)
+      return fail(ctx, IPM_E_ARG, "the analytic SG flux takes outflow or periodic boundaries and fixed degrees");
+    if (pb->p >= 1 && pb->p <= 3 && pb->degree >= 0 && pb->degree <= 40 &&
+        binom_basis(pb->p, pb->degree) > 16)
+      return fail(ctx, IPM_E_ARG, "the analytic SG flux takes at most 16 basis functions");
+  }
   if (pb->p < 1 || pb->p > 3) return fail(ctx, IPM_E_ARG, "p must be 1..3");
   if (pb->degree < 0 || pb->degree > 40) return fail(ctx, IPM_E_ARG, "degree must be 0..40");
   if (pb->quad_per_dim < 1 || pb->quad_per_dim > 64)
@@ -1261,6 +1273,8 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
   if (pb->n_retard > 0) ALLOC(P.d_retard, sizeof(Retard));
+  if (P.flux == IPM_FLUX_SG_ANALYTIC)
+    ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
   if (P.uneven) ALLOC(P.d_cellN[0], static_cast<size_t>(P.cells));
   if (P.adapt) ALLOC(P.d_cellN[1], static_cast<size_t>(P.cells));
   else P.d_cellN[1] = P.d_cellN[0];
@@ -1286,6 +1300,26 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
                            hipMemcpyHostToDevice, s));
   }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  std::vector<double> ctp;
+  if (P.d_ctp) {
+    // App. A: C_i = <phi phi^T phi_i>; the integrands have degree <= 3M, so a
+    // tensor Gauss-Legendre rule of 3M/2 + 1 points per dimension is exact
+    std::vector<double> cn, cw;
+    const int cq = tensor_rule(pb->p, (3 * pb->degree) / 2 + 1, cn, cw);
+    const std::vector<double> cphi = basis_table(pb->p, pb->degree, cq, cn);
+    const int N = P.N;
+    ctp.assign(static_cast<size_t>(N) * N * N, 0.0);
+    for (int q = 0; q < cq; ++q)
+      for (int i = 0; i < N; ++i) {
+        const double wi = cw[q] * cphi[static_cast<size_t>(q) * N + i];
+        for (int a = 0; a < N; ++a) {
+          const double wia = wi * cphi[static_cast<size_t>(q) * N + a];
+          for (int b = 0; b < N; ++b)
+            ctp[(static_cast<size_t>(i) * N + a) * N + b] += wia * cphi[static_cast<size_t>(q) * N + b];
+        }
+      }
+    CHK(hipMemcpyAsync(P.d_ctp, ctp.data(), ctp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   Retard hr{};
   if (P.d_retard) {
     hr.n = pb->n_retard;

@@ -68,7 +68,16 @@ struct UpdateParams {
   double* __restrict__ lam;          // [cells][M][N]
   const Retard* retard;              // null: no level cap
   unsigned cls_map;                  // 4 bits per size class: the class whose lists take its cells
+  const double* __restrict__ ctp;    // analytic SG flux: [N][N][N] <phi_i phi_a phi_b> (else null)
 };
+
+// index of the neighbour across side 0 (x-) or 1 (x+) of a 1D cell: the
+// cell itself at an outflow boundary, wrapped when periodic
+__device__ __forceinline__ int neighbour_1d(const UpdateParams& P, int ix, int side) {
+  const int j = side == 0 ? ix - 1 : ix + 1;
+  if (j >= 0 && j < P.nx) return j;
+  return P.bc[side] == kBcPeriodic ? (j + P.nx) % P.nx : ix;
+}
 
 // number of basis functions of total degree <= d in p dimensions,
 // binomial(d + p, p) (eq:numberBasisFcts); 0 for d = -1
@@ -139,7 +148,11 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
   for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) wphiL[k] = P.wphi[k];
   constexpr int CPW = 64 / G;
   const int groups = (blockDim.x >> 6) * CPW;
-  double* UT = wphiL + Q * kp;                           // per group [Q][M] updated nodes
+  const bool analytic = M == 1 && P.flux == kFluxSgAnalytic;
+  double* ctpL = wphiL + Q * kp;                         // analytic flux: [N][N][N]
+  if (analytic)
+    for (int k = threadIdx.x; k < N * N * N; k += blockDim.x) ctpL[k] = P.ctp[k];
+  double* UT = ctpL + (analytic ? N * N * N : 0);         // per group [Q][M] updated nodes
   double* UC = UT + static_cast<size_t>(groups) * Q * M;  // per group [Q][M] current nodes
   double* red = UC + static_cast<size_t>(groups) * Q * M;
 
@@ -199,8 +212,8 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         l[b] = first ? pw[b] : uw[q * M + b];
         rr[b] = first ? pe[b] : ue[q * M + b];
       }
-      numerical_flux<M>(P.flux, P.gamma, 0, c, rr, lfx, gr);
-      numerical_flux<M>(P.flux, P.gamma, 0, l, c, lfx, gl);
+      numerical_flux<M>(analytic ? kFluxLF : P.flux, P.gamma, 0, c, rr, lfx, gr);
+      numerical_flux<M>(analytic ? kFluxLF : P.flux, P.gamma, 0, l, c, lfx, gl);
 #pragma unroll
       for (int b = 0; b < M; ++b) acc[b] = c[b] - rx * (gr[b] - gl[b]);
       if (P.dim == 2) {
@@ -268,6 +281,15 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
     double d2 = 0.0, gsq[M];
 #pragma unroll
     for (int b = 0; b < M; ++b) gsq[b] = 0.0;
+    const double* lw = nullptr;
+    const double* lc = nullptr;
+    const double* le = nullptr;
+    if (analytic) {
+      const int ix = cell % P.nx;
+      lw = P.lam + static_cast<size_t>(neighbour_1d(P, ix, 0)) * N;
+      lc = P.lam + static_cast<size_t>(cell) * N;
+      le = P.lam + static_cast<size_t>(neighbour_1d(P, ix, 1)) * N;
+    }
     for (int k = r; k < M * N; k += G) {
       const int b = k / N, i = k % N;
       double v = 0.0, h = 0.0;
@@ -277,6 +299,27 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
           v = fma(ut[q * M + b], w, v);
           h = fma(uq[q * M + b], w, h);
         }
+      if (analytic && i < Nn) {
+        // App. A, eq:numFluxAnalytic on the duals (quadratic entropy: the
+        // dual is the SG moment vector): F_i(u) = u^T C_i u / 2,
+        // G = (F(u_l) + F(u_r)) / 2 - dx / (2 dt) (u_r - u_l)
+        double fw = 0.0, fc = 0.0, fe = 0.0;
+        for (int a = 0; a < N; ++a) {
+          const double* Ca = ctpL + (static_cast<size_t>(i) * N + a) * N;
+          double sw = 0.0, sc = 0.0, se = 0.0;
+          for (int bb = 0; bb < N; ++bb) {
+            sw = fma(Ca[bb], lw[bb], sw);
+            sc = fma(Ca[bb], lc[bb], sc);
+            se = fma(Ca[bb], le[bb], se);
+          }
+          fw = fma(0.5 * sw, lw[a], fw);
+          fc = fma(0.5 * sc, lc[a], fc);
+          fe = fma(0.5 * se, le[a], fe);
+        }
+        const double gr = 0.5 * (fc + fe) - lfx * (le[i] - lc[i]);
+        const double gl = 0.5 * (fw + fc) - lfx * (lc[i] - lw[i]);
+        v = lc[i] - dt / P.dx * (gr - gl);
+      }
       const size_t off = static_cast<size_t>(cell) * M * N + k;
       const double d = v - (k == r ? uold0 : P.uold[off]);
       d2 = fma(d, d, d2);

@@ -28,6 +28,8 @@ def _lam_samples(orc, ent, m, rng, k=8):
             assert ok
         elif ent == "log_barrier":
             lam = rng.uniform(-6, 6, size=1)
+        elif m >= 3:  # quadratic entropy of a gas: the dual is the state, physical
+            lam = _rand_euler_state(rng, m - 2)
         else:
             lam = rng.normal(size=m)
         out.append(lam)

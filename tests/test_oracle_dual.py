@@ -93,11 +93,21 @@ def test_quadratic_entropy_dual_is_the_moment_vector(orc, m_eq):
     spec["entropy"] = "quadratic"
     o = _oracle(orc, spec)
     rng = np.random.default_rng(4)
-    uhat = rng.normal(size=(o.m, o.N))
-    lam, st, its = o.dual_solve(uhat, rng.normal(size=(o.m, o.N)), one_shot=True)
+
+    def sample():
+        if m_eq == "burgers1d":
+            return rng.normal(size=(o.m, o.N))
+        # gas: a physical mean state with small higher modes, so that every
+        # node stays admissible (SG gas states must have rho, p > 0)
+        u = 0.01 * rng.normal(size=(o.m, o.N))
+        u[:, 0] = (1.0, 0.1, 2.5)
+        return u
+
+    uhat = sample()
+    lam, st, its = o.dual_solve(uhat, sample(), one_shot=True)
     assert st == 0 and its == 1
     assert np.max(np.abs(lam - uhat)) < 1e-13 * (1 + np.max(np.abs(uhat)))
-    lam2, st2, its2 = o.dual_solve(uhat, rng.normal(size=(o.m, o.N)))
+    lam2, st2, its2 = o.dual_solve(uhat, sample())
     assert st2 == 0 and its2 == 1
 
 
