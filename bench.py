@@ -415,14 +415,66 @@ def steady_form(args):
     }
 
 
+def sg_form(args):
+    """Stochastic-Galerkin baseline (App. A): Burgers' equation with an
+    uncertain shock (8192 cells, degree 9, N = 10) stepped as IPM with the
+    log-barrier entropy, as SG (quadratic entropy) with the kinetic
+    Lax-Friedrichs flux on 14 nodes (exact for SG), and as SG with the
+    analytic triple-product flux; time per step of each."""
+    import torch
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    nx, steps = 8192, args.sg_steps
+    base = W.burgers_shock(nx=nx, degree=9, qpd=14, t_end=0.0)
+    sg = dict(base, entropy="quadratic")
+    variants = [("IPM_log_barrier", base), ("SG_kinetic_LF", sg),
+                ("SG_analytic_flux", dict(sg, flux="sg_analytic"))]
+    nodes, _ = binding.quadrature(1, 14)
+    res = {}
+    for name, sp in variants:
+        pid = ctx.set_problem(sp, ic_nodal=W.ic_nodal(sp, nodes))
+        ctx.step(pid, 10, wait=True)
+        b = ctx.query(pid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(pid, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        a = ctx.query(pid)
+        assert a["status"] == 0, (name, a)
+        ctx.timing(True)
+        ctx.step(pid, 50)
+        tm = ctx.timing(False)
+        ctx.release(pid)
+        res[name] = {"value": nx * steps / el, "ms_per_step": el / steps * 1e3,
+                     "dual_us_per_step": tm["dual_ms"] / 50 * 1e3,
+                     "update_us_per_step": tm["update_ms"] / 50 * 1e3,
+                     "kbar": (a["newton_iters"] - b["newton_iters"]) / (nx * steps)}
+        print("sg form: %s %.4f ms per step" % (name, res[name]["ms_per_step"]), file=sys.stderr,
+              flush=True)
+    ctx.close()
+    r = res["SG_analytic_flux"]
+    return {
+        "metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": 10, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "burgers_shock_nx%d_deg9_sg_baseline" % nx, "cells": nx, "N": 10,
+                   "Q": 14, "parallelism": "single-gpu"},
+        "variants": res,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt", "steady"],
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt", "steady",
+                                       "sg"],
                     default="plain",
                     help="plain: the Sod throughput line (default); batch / serve / precision / "
                          "adapt / steady: the batching, serving, precision, adaptive and "
                          "steady (one-shot, retardation) forms")
     ap.add_argument("--steady-nx", type=int, default=2048)
+    ap.add_argument("--sg-steps", type=int, default=400)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -463,6 +515,9 @@ def main():
         return
     if args.form == "steady":
         print(json.dumps(steady_form(args)), flush=True)
+        return
+    if args.form == "sg":
+        print(json.dumps(sg_form(args)), flush=True)
         return
 
     import torch
