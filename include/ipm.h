@@ -79,6 +79,14 @@ enum { IPM_BC_OUTFLOW = 0, IPM_BC_PERIODIC = 1, IPM_BC_DIRICHLET = 2 };
 /* arithmetic of the Hessian assembly (Newton update, Cholesky solve, gradient
    and the tau test are always FP64) */
 enum { IPM_PREC_FP64 = 0, IPM_PREC_FP32 = 1, IPM_PREC_BF16 = 2 };
+/* quadrature rule for xi ~ U(-1,1)^p (Sec. 3.1 <.>_Q; Sec. 7 compares
+   tensorized and sparse Clenshaw-Curtis grids): tensor Gauss-Legendre or
+   tensor Clenshaw-Curtis with quad_per_dim points per dimension, or the
+   Smolyak sparse grid of nested Clenshaw-Curtis rules (1, 3, 5, 9, ...
+   points) of level quad_per_dim (0..11; p = 3: 1, 7, 25, 69, 177, 441, ...
+   nodes).  Sparse grids carry negative weights, so the dual Hessian can
+   lose definiteness (the failure Sec. 7 reports from order 3 on). */
+enum { IPM_QUAD_GAUSS_LEGENDRE = 0, IPM_QUAD_CLENSHAW_CURTIS = 1, IPM_QUAD_CC_SPARSE = 2 };
 
 typedef struct {
   int device;               /* HIP device ordinal */
@@ -136,6 +144,7 @@ typedef struct {
   int n_retard;
   const int *retard_degree;
   const double *retard_eps;
+  int quad_rule;            /* IPM_QUAD_*; 0 (Gauss-Legendre) for the fields above */
 } ipm_problem;
 
 typedef struct {
@@ -176,6 +185,16 @@ ipm_status ipm_destroy(ipm_ctx *ctx);
    nodes [Q][p] with the first coordinate varying slowest.  cap = capacity of
    weights in entries; returns IPM_E_ARG if Q > cap.  Host only, no device. */
 ipm_status ipm_quadrature(int p, int quad_per_dim, double *nodes, double *weights, int cap);
+
+/* Number of nodes of a quadrature rule (IPM_QUAD_*, param = points per
+   dimension or sparse level), 0 for invalid arguments.  Host only. */
+int ipm_quadrature_size(int rule, int p, int param);
+
+/* Nodes [Q][p] and weights [Q] (sum 1) of a rule, as problems with that
+   quad_rule use them; cap = capacity of weights.  Tensor rules order nodes
+   with the first coordinate slowest; sparse grids in ascending order of the
+   nodes' indices on the finest Clenshaw-Curtis grid.  Host only. */
+ipm_status ipm_quadrature_rule(int rule, int p, int param, double *nodes, double *weights, int cap);
 
 /* Number of basis functions N = binomial(degree + p, p). */
 int ipm_basis_size(int p, int degree);

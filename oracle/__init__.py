@@ -6,6 +6,7 @@ See ``ipm_oracle.h`` for what the oracle computes and how it is pinned.
 """
 from .oracle import (  # noqa: F401
     Oracle, build, load, num_basis, gauss_legendre, quadrature, multi_indices,
-    basis_eval, closure, entropy_grad, entropy, indicator, select_degrees, EQ, ENT, FLUX, BC,
+    basis_eval, closure, entropy_grad, entropy, indicator, select_degrees, clenshaw_curtis,
+    EQ, ENT, FLUX, BC, QUAD,
     STATUS,
 )

@@ -136,6 +136,189 @@ int orc_quadrature(int p, int qpd, double *nodes, double *w)
   return Q;
 }
 
+/* Clenshaw-Curtis: nodes cos(pi k/(n-1)) (ascending), weights as the
+   integrals over [-1, 1] of the Lagrange polynomials of the nodes, each
+   integrated by Gauss-Legendre (exact: degree n-1).  n = 1: midpoint.
+   w = NULL: nodes only. */
+int orc_clenshaw_curtis(int n, double *x, double *w)
+{
+  if (n < 1) return 0;
+  if (n == 1) {
+    x[0] = 0.0;
+    if (w) w[0] = 2.0;
+    return 1;
+  }
+  for (int k = 0; k < n; ++k) x[k] = -cos(M_PI * k / (n - 1));
+  x[0] = -1.0;
+  x[n - 1] = 1.0;
+  if ((n - 1) % 2 == 0) x[(n - 1) / 2] = 0.0;
+  if (!w) return n;
+  double *gx = (double *)malloc(sizeof(double) * n), *gw = (double *)malloc(sizeof(double) * n);
+  orc_gauss_legendre(n, gx, gw);
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int q = 0; q < n; ++q) {
+      double l = 1.0;
+      for (int j = 0; j < n; ++j)
+        if (j != k) l *= (gx[q] - x[j]) / (x[k] - x[j]);
+      s += gw[q] * l;
+    }
+    w[k] = s;
+  }
+  free(gx);
+  free(gw);
+  return n;
+}
+
+/* one contribution to a sparse grid: fine-grid indices packed in a key */
+typedef struct {
+  long long key;
+  double w;
+} contrib_t;
+
+static int cmp_contrib(const void *a, const void *b)
+{
+  long long ka = ((const contrib_t *)a)->key, kb = ((const contrib_t *)b)->key;
+  return ka < kb ? -1 : ka > kb ? 1 : 0;
+}
+
+/* Smolyak sparse grid of level L from the nested Clenshaw-Curtis rules U_l
+   with m(1) = 1, m(l) = 2^(l-1) + 1 points, as the sum over multi-levels
+   l_1 + ... + l_p <= L + p of the tensor products of the difference rules
+   D_l = U_l - U_(l-1) (U_0 = 0).  Every node lies on the finest grid
+   (2^L + 1 points per dimension); contributions are merged on it.  If
+   nodes is NULL only the node count is returned. */
+static int cc_sparse(int p, int L, double *nodes, double *wts)
+{
+  int fine = (1 << L) + 1;
+  double *xf = (double *)malloc(sizeof(double) * fine);
+  orc_clenshaw_curtis(fine, xf, NULL);
+  /* 1D difference rules on fine indices: dn[l], di[l][], dw[l][] */
+  int Lmax = L + 1;
+  int *dn = (int *)calloc(Lmax + 1, sizeof(int));
+  int **di = (int **)calloc(Lmax + 1, sizeof(int *));
+  double **dw = (double **)calloc(Lmax + 1, sizeof(double *));
+  for (int l = 1; l <= Lmax; ++l) {
+    di[l] = (int *)calloc(fine, sizeof(int));
+    dw[l] = (double *)calloc(fine, sizeof(double));
+    double *acc = (double *)calloc(fine, sizeof(double));
+    char *used = (char *)calloc(fine, 1);
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      int lev = l - sgn;
+      if (lev < 1) continue;
+      int m = lev == 1 ? 1 : (1 << (lev - 1)) + 1;
+      double *x = (double *)malloc(sizeof(double) * m), *w = (double *)calloc(m, sizeof(double));
+      orc_clenshaw_curtis(m, x, nodes ? w : NULL);  /* counting needs no weights */
+      for (int k = 0; k < m; ++k) {
+        int g = m == 1 ? (fine - 1) / 2 : k * ((fine - 1) / (m - 1));
+        acc[g] += (sgn ? -1.0 : 1.0) * 0.5 * w[k];
+        used[g] = 1;
+      }
+      free(x);
+      free(w);
+    }
+    for (int g = 0; g < fine; ++g)
+      if (used[g]) {
+        di[l][dn[l]] = g;
+        dw[l][dn[l]] = acc[g];
+        dn[l]++;
+      }
+    free(acc);
+    free(used);
+  }
+  size_t cap = 1024, cnt = 0;
+  contrib_t *c = (contrib_t *)malloc(sizeof(contrib_t) * cap);
+  int lv[3] = {1, 1, 1};
+  for (;;) {
+    int s = 0;
+    for (int d = 0; d < p; ++d) s += lv[d];
+    if (s <= L + p) {
+      int ix[3] = {0, 0, 0};
+      for (;;) {
+        long long key = 0;
+        double w = 1.0;
+        for (int d = 0; d < p; ++d) {
+          key = key * fine + di[lv[d]][ix[d]];
+          w *= dw[lv[d]][ix[d]];
+        }
+        if (cnt == cap) {
+          cap *= 2;
+          c = (contrib_t *)realloc(c, sizeof(contrib_t) * cap);
+        }
+        c[cnt].key = key;
+        c[cnt].w = w;
+        cnt++;
+        int d = p - 1;
+        while (d >= 0 && ++ix[d] == dn[lv[d]]) ix[d--] = 0;
+        if (d < 0) break;
+      }
+    }
+    int d = p - 1;
+    while (d >= 0 && ++lv[d] > Lmax) lv[d--] = 1;
+    if (d < 0) break;
+  }
+  qsort(c, cnt, sizeof(contrib_t), cmp_contrib);
+  int Q = 0;
+  for (size_t i = 0; i < cnt;) {
+    size_t j = i;
+    double w = 0.0;
+    while (j < cnt && c[j].key == c[i].key) w += c[j++].w;
+    if (nodes) {
+      long long r = c[i].key;
+      for (int d = p - 1; d >= 0; --d) {
+        nodes[(size_t)Q * p + d] = xf[r % fine];
+        r /= fine;
+      }
+      wts[Q] = w;
+    }
+    Q++;
+    i = j;
+  }
+  free(c);
+  for (int l = 1; l <= Lmax; ++l) {
+    free(di[l]);
+    free(dw[l]);
+  }
+  free(dn);
+  free(di);
+  free(dw);
+  free(xf);
+  return Q;
+}
+
+int orc_quadrature_size(int rule, int p, int param)
+{
+  if (p < 1 || p > 3) return 0;
+  if (rule == ORC_QUAD_CC_SPARSE) return param >= 0 ? cc_sparse(p, param, NULL, NULL) : 0;
+  if (param < 1) return 0;
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= param;
+  return Q;
+}
+
+int orc_quadrature_rule(int rule, int p, int param, double *nodes, double *w)
+{
+  if (rule == ORC_QUAD_GL) return orc_quadrature(p, param, nodes, w);
+  if (rule == ORC_QUAD_CC_SPARSE) return cc_sparse(p, param, nodes, w);
+  /* tensor Clenshaw-Curtis, first coordinate slowest, weights / 2 per dim */
+  double *x = (double *)malloc(sizeof(double) * param), *w1 = (double *)malloc(sizeof(double) * param);
+  orc_clenshaw_curtis(param, x, w1);
+  int Q = orc_quadrature_size(rule, p, param);
+  for (int q = 0; q < Q; ++q) {
+    int r = q;
+    w[q] = 1.0;
+    for (int k = p - 1; k >= 0; --k) {
+      int d = r % param;
+      r /= param;
+      nodes[(size_t)q * p + k] = x[d];
+      w[q] *= 0.5 * w1[d];
+    }
+  }
+  free(x);
+  free(w1);
+  return Q;
+}
+
 static void gen_indices(int p, int left, int pos, int *cur, int *out, int *cnt)
 {
   if (pos == p - 1) {
@@ -682,8 +865,7 @@ orc_state *orc_create(const orc_problem *pb, const signed char *cell_degree,
   if (S->dim == 1) S->pb.ny = 1;
   S->N = orc_num_basis(pb->p, pb->degree);
   S->n = S->m * S->N;
-  int Q = 1;
-  for (int k = 0; k < pb->p; ++k) Q *= pb->quad_per_dim;
+  int Q = orc_quadrature_size(pb->quad_rule, pb->p, pb->quad_per_dim);
   S->Q = Q;
   S->cells = S->pb.nx * S->pb.ny;
   S->dx = (pb->x1 - pb->x0) / pb->nx;
@@ -692,7 +874,7 @@ orc_state *orc_create(const orc_problem *pb, const signed char *cell_degree,
   S->nodes = (double *)malloc(sizeof(double) * Q * pb->p);
   S->w = (double *)malloc(sizeof(double) * Q);
   S->Phi = (double *)malloc(sizeof(double) * Q * S->N);
-  orc_quadrature(pb->p, pb->quad_per_dim, S->nodes, S->w);
+  orc_quadrature_rule(pb->quad_rule, pb->p, pb->quad_per_dim, S->nodes, S->w);
   orc_basis_eval(pb->p, pb->degree, Q, S->nodes, S->Phi);
   if (pb->flux == ORC_FLUX_SG_ANALYTIC) {
     /* App. A: C_i = <phi phi^T phi_i>, integrands of degree <= 3M, by a

@@ -39,6 +39,10 @@ enum { ORC_ENT_QUADRATIC = 0, ORC_ENT_LOG_BARRIER = 1, ORC_ENT_EULER = 2 };
    entropy: the dual is the SG moment vector); 1D Burgers only */
 enum { ORC_FLUX_LF = 0, ORC_FLUX_RUSANOV = 1, ORC_FLUX_SG_ANALYTIC = 2 };
 enum { ORC_BC_OUTFLOW = 0, ORC_BC_PERIODIC = 1, ORC_BC_DIRICHLET = 2 };
+/* quadrature for xi ~ U(-1,1)^p: tensor Gauss-Legendre, tensor
+   Clenshaw-Curtis (points per dimension), Clenshaw-Curtis sparse grid
+   (Smolyak, nested 1, 3, 5, 9, ... point rules; the parameter is the level) */
+enum { ORC_QUAD_GL = 0, ORC_QUAD_CC = 1, ORC_QUAD_CC_SPARSE = 2 };
 
 /* status bits, sticky per problem */
 enum {
@@ -77,6 +81,7 @@ typedef struct {
   int n_retard;
   int retard_degree[ORC_MAX_RETARD];
   double retard_eps[ORC_MAX_RETARD];
+  int quad_rule;         /* ORC_QUAD_*; quad_per_dim is the sparse level for ORC_QUAD_CC_SPARSE */
 } orc_problem;
 
 typedef struct {
@@ -93,6 +98,9 @@ int orc_num_basis(int p, int degree);
 int orc_gauss_legendre(int n, double *x, double *w);
 int orc_quadrature(int p, int qpd, double *nodes /*[Q][p]*/, double *w /*[Q], sum 1*/);
 int orc_multi_indices(int p, int degree, int *idx /*[N][p]*/);
+int orc_clenshaw_curtis(int n, double *x, double *w /*sum 2*/);
+int orc_quadrature_size(int rule, int p, int param);
+int orc_quadrature_rule(int rule, int p, int param, double *nodes /*[Q][p]*/, double *w /*sum 1*/);
 void orc_basis_eval(int p, int degree, int Q, const double *nodes, double *Phi /*[Q][N]*/);
 
 /* Smoothness indicator of Sec. 5 (eq:errorIndicator) for one scalar field

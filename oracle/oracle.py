@@ -19,6 +19,7 @@ EQ = {"burgers1d": 0, "euler1d": 1, "euler2d": 2}
 ENT = {"quadratic": 0, "log_barrier": 1, "euler": 2}
 FLUX = {"lf": 0, "rusanov": 1, "sg_analytic": 2}
 BC = {"outflow": 0, "periodic": 1, "dirichlet": 2}
+QUAD = {"gl": 0, "cc": 1, "cc_sparse": 2}
 STATUS = {"newton": 1, "realizability": 2, "nonfinite": 4, "cholesky": 8, "linesearch": 16}
 
 
@@ -36,6 +37,7 @@ class Problem(C.Structure):
         ("adapt", C.c_int), ("min_degree", C.c_int),
         ("delta_lo", C.c_double), ("delta_hi", C.c_double),
         ("n_retard", C.c_int), ("retard_degree", C.c_int * 16), ("retard_eps", C.c_double * 16),
+        ("quad_rule", C.c_int),
     ]
 
 
@@ -75,6 +77,9 @@ def load():
     lib.orc_num_basis.argtypes = [i, i]
     lib.orc_gauss_legendre.argtypes = [i, dp, dp]
     lib.orc_quadrature.argtypes = [i, i, dp, dp]
+    lib.orc_clenshaw_curtis.argtypes = [i, dp, dp]
+    lib.orc_quadrature_size.argtypes = [i, i, i]
+    lib.orc_quadrature_rule.argtypes = [i, i, i, dp, dp]
     lib.orc_multi_indices.argtypes = [i, i, ip]
     lib.orc_basis_eval.argtypes = [i, i, i, dp, dp]
     lib.orc_basis_eval.restype = None
@@ -127,11 +132,21 @@ def gauss_legendre(n):
     return x, w
 
 
-def quadrature(p, qpd):
-    Q = qpd ** p
+def quadrature(p, qpd, rule="gl"):
+    """Nodes [Q][p] and weights (sum 1) of a rule: gl / cc (qpd points per
+    dimension) or cc_sparse (qpd = level)."""
+    lib = load()
+    Q = lib.orc_quadrature_size(QUAD[rule], p, qpd)
     nodes, w = np.zeros((Q, p)), np.zeros(Q)
-    load().orc_quadrature(p, qpd, _ptr(nodes), _ptr(w))
+    lib.orc_quadrature_rule(QUAD[rule], p, qpd, _ptr(nodes), _ptr(w))
     return nodes, w
+
+
+def clenshaw_curtis(n):
+    """n-point Clenshaw-Curtis rule on [-1, 1] (weights sum to 2)."""
+    x, w = np.zeros(n), np.zeros(n)
+    load().orc_clenshaw_curtis(n, _ptr(x), _ptr(w))
+    return x, w
 
 
 def multi_indices(p, degree):
@@ -212,6 +227,7 @@ def make_problem(spec):
     pb.steady_eps = spec.get("steady_eps", 0.0)
     pb.max_newton = spec.get("max_newton", 100)
     pb.one_shot = int(spec.get("one_shot", 0))
+    pb.quad_rule = QUAD[spec.get("quad_rule", "gl")]
     pb.adapt = int(spec.get("adapt", 0))
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)
@@ -236,7 +252,8 @@ class Oracle:
         self.pb = make_problem(spec)
         self.m = {0: 1, 1: 3, 2: 4}[self.pb.equation]
         self.N = num_basis(self.pb.p, self.pb.degree)
-        self.nodes, self.w = quadrature(self.pb.p, self.pb.quad_per_dim)
+        self.nodes, self.w = quadrature(self.pb.p, self.pb.quad_per_dim,
+                                        spec.get("quad_rule", "gl"))
         self.Q = self.nodes.shape[0]
         ny = self.pb.ny if self.pb.equation == 2 else 1
         self.cells = self.pb.nx * ny

@@ -17,6 +17,7 @@ ENT = {"quadratic": 0, "log_barrier": 1, "euler": 2}
 FLUX = {"lf": 0, "rusanov": 1, "sg_analytic": 2}
 BC = {"outflow": 0, "periodic": 1, "dirichlet": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+QUAD = {"gl": 0, "cc": 1, "cc_sparse": 2}
 STATUS = {0: "ok", -1: "arg", -2: "state", -3: "nomem", -4: "realizability", -5: "newton",
           -6: "nonfinite", -7: "device", -8: "busy"}
 
@@ -48,7 +49,7 @@ class Problem(C.Structure):
         ("adapt", C.c_int), ("min_degree", C.c_int),
         ("delta_lo", C.c_double), ("delta_hi", C.c_double),
         ("n_retard", C.c_int), ("retard_degree", C.POINTER(C.c_int)),
-        ("retard_eps", C.POINTER(C.c_double)),
+        ("retard_eps", C.POINTER(C.c_double)), ("quad_rule", C.c_int),
     ]
 
 
@@ -74,7 +75,7 @@ EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
            "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_cell_degrees",
-           "ipm_last_error"]
+           "ipm_quadrature_size", "ipm_quadrature_rule", "ipm_last_error"]
 
 _lib = None
 
@@ -109,6 +110,8 @@ def load(path=None):
     lib.ipm_select_degrees.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double,
                                        P(C.c_int8)]
     lib.ipm_cell_degrees.argtypes = [vp, C.c_int, P(C.c_int8), C.c_size_t]
+    lib.ipm_quadrature_size.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.ipm_quadrature_rule.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int]
     lib.ipm_last_error.argtypes = [vp]
     lib.ipm_last_error.restype = C.c_char_p
     _lib = lib
@@ -119,11 +122,13 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
 
 
-def quadrature(p, qpd):
+def quadrature(p, qpd, rule="gl"):
+    """Nodes [Q][p] and weights of the problem's rule (``rule``: gl, cc or
+    cc_sparse; qpd = points per dimension or the sparse level)."""
     lib = load()
-    Q = qpd ** p
-    nodes, w = np.zeros((Q, p)), np.zeros(Q)
-    st = lib.ipm_quadrature(p, qpd, _dptr(nodes), _dptr(w), Q)
+    Q = lib.ipm_quadrature_size(QUAD[rule], p, qpd)
+    nodes, w = np.zeros((max(Q, 1), p)), np.zeros(max(Q, 1))
+    st = lib.ipm_quadrature_rule(QUAD[rule], p, qpd, _dptr(nodes), _dptr(w), Q)
     if st != 0:
         raise IpmError(st, lib.ipm_last_error(None).decode())
     return nodes, w
@@ -172,6 +177,7 @@ def problem_struct(spec, keep):
     pb.max_newton = spec.get("max_newton", 100)
     pb.one_shot = int(spec.get("one_shot", 0))
     pb.precision = PREC[spec.get("precision", "fp64")]
+    pb.quad_rule = QUAD[spec.get("quad_rule", "gl")]
     pb.adapt = int(spec.get("adapt", 0))
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)

@@ -89,6 +89,7 @@ struct Problem {
   size_t charged = 0;  // bytes charged against the context's budget
   int upd_blocks = 1, dual_blocks = 1;
   size_t upd_lds = 0;
+  int upd_waves = 4;  // wavefronts per update block (fewer when the node tiles fill LDS)
 };
 
 // One launch of a batched step: a Newton launch of one kernel template over
@@ -389,7 +390,16 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     }
   }
   P.UG = pow2_at_least(std::min(64, std::max(P.Q, n)), 16);
-  const int ucpb = 4 * (64 / P.UG);
+  // update blocks of 4 wavefronts, or fewer when the per-cell node tiles of
+  // many quadrature nodes would not fit LDS
+  auto upd_lds_for = [&](int waves) {
+    const size_t cpb = static_cast<size_t>(waves) * (64 / P.UG);
+    return sizeof(double) * (static_cast<size_t>(P.Q) * P.kp + 2 * cpb * P.Q * P.M + 256 +
+                             (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
+  };
+  P.upd_waves = 4;
+  while (P.upd_waves > 1 && upd_lds_for(P.upd_waves) > ctx->max_lds) P.upd_waves >>= 1;
+  const int ucpb = P.upd_waves * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
   P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
                                 2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
@@ -617,7 +627,7 @@ ipm_status enqueue_step(ipm_ctx* ctx, Problem& P) {
   }
   UpdateParams u = update_params(P, parity);
   UpdFn fn = pick_update(P.M, P.UG);
-  hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(256), P.upd_lds, ctx->stream, u);
+  hipLaunchKernelGGL(fn, dim3(P.upd_blocks), dim3(64 * P.upd_waves), P.upd_lds, ctx->stream, u);
   HIPCHK(ctx, hipGetLastError());
   if (ctx->timing) HIPCHK(ctx, hipEventRecord(e3, ctx->stream));
   if (P.steady_eps > 0.0) {
@@ -722,6 +732,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
     std::map<std::string, const void*> nfn;
     std::map<std::string, std::vector<UEntry>> ug;
     std::map<std::string, const void*> ufn;
+    std::map<std::string, int> uthreads;
     std::vector<BatchLaunch> resid;
     for (int id : ids) {
       Problem& P = *get(ctx, id);
@@ -759,9 +770,11 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         nfn[key] = pick_newton_batched(P.M, D.NP, D.T, D.prec);
         if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
       }
-      const std::string ukey = std::to_string(P.M) + ":" + std::to_string(P.UG);
+      const std::string ukey = std::to_string(P.M) + ":" + std::to_string(P.UG) + ":" +
+                               std::to_string(P.upd_waves);
       ug[ukey].push_back({update_params(P, parity), P.upd_blocks, P.upd_lds});
       ufn[ukey] = pick_update_batched(P.M, P.UG);
+      uthreads[ukey] = 64 * P.upd_waves;
       if (P.steady_eps > 0.0) {
         BatchLaunch L;
         L.kind = 2;
@@ -796,7 +809,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
       L.kind = 1;
       L.fn = ufn[kv.first];
       if (!L.fn) return fail(ctx, IPM_E_ARG, "no batched update kernel for this size");
-      L.threads = 256;
+      L.threads = uthreads[kv.first];
       L.pofs = ups.size();
       L.bofs = static_cast<int>(begins.size());
       L.n = static_cast<int>(kv.second.size());
@@ -1008,8 +1021,12 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
   }
   if (pb->p < 1 || pb->p > 3) return fail(ctx, IPM_E_ARG, "p must be 1..3");
   if (pb->degree < 0 || pb->degree > 40) return fail(ctx, IPM_E_ARG, "degree must be 0..40");
-  if (pb->quad_per_dim < 1 || pb->quad_per_dim > 64)
+  if (pb->quad_rule < IPM_QUAD_GAUSS_LEGENDRE || pb->quad_rule > IPM_QUAD_CC_SPARSE)
+    return fail(ctx, IPM_E_ARG, "quad_rule out of range");
+  if (pb->quad_rule != IPM_QUAD_CC_SPARSE && (pb->quad_per_dim < 1 || pb->quad_per_dim > 64))
     return fail(ctx, IPM_E_ARG, "quad_per_dim must be 1..64");
+  if (pb->quad_rule == IPM_QUAD_CC_SPARSE && (pb->quad_per_dim < 0 || pb->quad_per_dim > 11))
+    return fail(ctx, IPM_E_ARG, "the sparse-grid level must be 0..11");
   if (pb->precision < 0 || pb->precision > 2) return fail(ctx, IPM_E_ARG, "precision out of range");
   if (pb->precision == IPM_PREC_FP32)
     return fail(ctx, IPM_E_ARG,
@@ -1043,8 +1060,8 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
       return fail(ctx, IPM_E_ARG, "adaptivity needs 1 <= min_degree <= degree");
     if (!(pb->delta_lo <= pb->delta_hi))
       return fail(ctx, IPM_E_ARG, "adaptivity needs delta_lo <= delta_hi");
-    if (pb->quad_per_dim < pb->degree + 1)
-      return fail(ctx, IPM_E_ARG, "adaptivity needs quad_per_dim >= degree + 1");
+    if (pb->quad_rule != IPM_QUAD_GAUSS_LEGENDRE || pb->quad_per_dim < pb->degree + 1)
+      return fail(ctx, IPM_E_ARG, "adaptivity needs the Gauss-Legendre rule with quad_per_dim >= degree + 1");
   }
   if (pb->n_retard != 0) {
     if (!pb->adapt || !(pb->steady_eps > 0.0))
@@ -1071,6 +1088,30 @@ const char* ipm_last_error(const ipm_ctx* ctx) {
 int ipm_basis_size(int p, int degree) {
   if (p < 1 || degree < 0) return 0;
   return binom_basis(p, degree);
+}
+
+int ipm_quadrature_size(int rule, int p, int param) {
+  if (p < 1 || p > 3 || rule < 0 || rule > 2) return 0;
+  if (rule == IPM_QUAD_CC_SPARSE) {
+    if (param < 0 || param > 11) return 0;
+    std::vector<double> x, w;
+    return cc_sparse_rule(p, param, x, w);
+  }
+  if (param < 1 || param > 64) return 0;
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= param;
+  return Q;
+}
+
+ipm_status ipm_quadrature_rule(int rule, int p, int param, double* nodes, double* weights, int cap) {
+  const int Q = ipm_quadrature_size(rule, p, param);
+  if (Q == 0 || !nodes || !weights) return fail(nullptr, IPM_E_ARG, "ipm_quadrature_rule: bad arguments");
+  if (Q > cap) return fail(nullptr, IPM_E_ARG, "ipm_quadrature_rule: capacity too small");
+  std::vector<double> x, w;
+  quadrature_rule(rule, p, param, x, w);
+  std::memcpy(nodes, x.data(), sizeof(double) * Q * p);
+  std::memcpy(weights, w.data(), sizeof(double) * Q);
+  return IPM_OK;
 }
 
 ipm_status ipm_quadrature(int p, int quad_per_dim, double* nodes, double* weights, int cap) {
@@ -1104,8 +1145,7 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
   if (!pb) return 0;
   const int M = components(pb->equation);
   const int N = binom_basis(pb->p, pb->degree);
-  int Q = 1;
-  for (int k = 0; k < pb->p; ++k) Q *= pb->quad_per_dim;
+  const int Q = std::max(1, ipm_quadrature_size(pb->quad_rule, pb->p, pb->quad_per_dim));
   const size_t cells = static_cast<size_t>(pb->nx) * (pb->equation == IPM_EULER_2D ? pb->ny : 1);
   const size_t n = static_cast<size_t>(M) * N;
   return sizeof(double) * (3 * cells * n + cells * Q * M + 2 * static_cast<size_t>(Q) * (N + 64) +
@@ -1167,7 +1207,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.degree = pb->degree;
   P.N = binom_basis(pb->p, pb->degree);
   std::vector<double> nodes, w;
-  P.Q = tensor_rule(pb->p, pb->quad_per_dim, nodes, w);
+  P.Q = quadrature_rule(pb->quad_rule, pb->p, pb->quad_per_dim, nodes, w);
   P.nx = pb->nx;
   P.ny = P.dim == 2 ? pb->ny : 1;
   P.cells = P.nx * P.ny;

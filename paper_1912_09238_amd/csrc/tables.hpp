@@ -6,8 +6,10 @@
 // built once per problem and uploaded.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 namespace ipm {
@@ -76,6 +78,152 @@ inline int tensor_rule(int p, int qpd, std::vector<double>& nodes, std::vector<d
     }
   }
   return Q;
+}
+
+// Clenshaw-Curtis rule of n points on [-1, 1] (the experiments of Sec. 7 use
+// it for tensor and sparse grids): nodes cos(pi k / (n-1)) ascending, weights
+// c_k / (n-1) * (1 - sum_{j=1}^{(n-1)/2} b_j cos(2 pi j k / (n-1)) / (4 j^2 - 1))
+// with c_k = 1 at the end points (2 inside) and b_j = 1 for j = (n-1)/2 when
+// n-1 is even (2 otherwise); n = 1 is the midpoint rule.  Weights sum to 2.
+inline void clenshaw_curtis(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 2.0);
+  if (n == 1) return;
+  const double pi = 3.14159265358979323846;
+  const int N = n - 1;
+  for (int k = 0; k <= N; ++k) {
+    double s = 0.0;
+    for (int j = 1; j <= N / 2; ++j) {
+      const double b = (2 * j == N) ? 1.0 : 2.0;
+      s += b * std::cos(2.0 * pi * j * k / N) / (4.0 * j * j - 1.0);
+    }
+    const double c = (k == 0 || k == N) ? 1.0 : 2.0;
+    x[N - k] = std::cos(pi * k / N);
+    w[N - k] = c / N * (1.0 - s);
+  }
+  x[0] = -1.0;  // exact end points and centre
+  x[N] = 1.0;
+  if (N % 2 == 0) x[N / 2] = 0.0;
+}
+
+// Tensor rule of n points per dimension from a 1D rule (same node order and
+// weight normalisation as tensor_rule).
+inline int tensor_from_1d(int p, const std::vector<double>& x, const std::vector<double>& w,
+                          std::vector<double>& nodes, std::vector<double>& wts) {
+  const int n = static_cast<int>(x.size());
+  int Q = 1;
+  for (int k = 0; k < p; ++k) Q *= n;
+  nodes.assign(static_cast<size_t>(Q) * p, 0.0);
+  wts.assign(Q, 1.0);
+  for (int q = 0; q < Q; ++q) {
+    int r = q;
+    for (int k = p - 1; k >= 0; --k) {
+      const int d = r % n;
+      r /= n;
+      nodes[static_cast<size_t>(q) * p + k] = x[d];
+      wts[q] *= 0.5 * w[d];
+    }
+  }
+  return Q;
+}
+
+// Smolyak sparse grid of level L from the nested Clenshaw-Curtis rules with
+// 1, 3, 5, 9, ..., 2^(l-1) + 1 points at levels l = 1, 2, 3, ...: the
+// combination sum over l_1 + ... + l_p = s, s in [max(p, L+1), L+p], of
+// (-1)^(L+p-s) binom(p-1, L+p-s) U_{l_1} x ... x U_{l_p}.  The rules are
+// nested, so every node is a point of the finest grid (2^L + 1 points per
+// dimension) and coinciding nodes are merged by their grid indices.  Nodes
+// in ascending order of those indices; weights sum to one.
+inline int cc_sparse_rule(int p, int L, std::vector<double>& nodes, std::vector<double>& wts) {
+  const int fine = (1 << L) + 1;  // finest rule's points
+  std::vector<double> xf, wf;
+  clenshaw_curtis(fine, xf, wf);
+  auto key_of = [&](const std::vector<int>& g) {
+    long long k = 0;
+    for (int d = 0; d < p; ++d) k = k * fine + g[d];
+    return k;
+  };
+  std::vector<double> sum_w;
+  std::vector<long long> sum_k;
+  std::vector<int> l(p, 1);
+  // enumerate l in [1, L+1]^p with sum in range (odometer)
+  while (true) {
+    int s = 0;
+    for (int d = 0; d < p; ++d) s += l[d];
+    if (s >= std::max(p, L + 1) && s <= L + p) {
+      const int e = L + p - s;
+      double coef = 1.0;
+      for (int k = 1; k <= e; ++k) coef = coef * (p - k) / k;  // binom(p-1, e)
+      if (e % 2) coef = -coef;
+      // tensor product of the levels' rules
+      std::vector<std::vector<double>> wl(p);
+      std::vector<std::vector<int>> gl(p);
+      for (int d = 0; d < p; ++d) {
+        const int m = l[d] == 1 ? 1 : (1 << (l[d] - 1)) + 1;
+        std::vector<double> xx, ww;
+        clenshaw_curtis(m, xx, ww);
+        wl[d] = ww;
+        gl[d].resize(m);
+        for (int k = 0; k < m; ++k) gl[d][k] = m == 1 ? (fine - 1) / 2 : k * ((fine - 1) / (m - 1));
+      }
+      std::vector<int> c(p, 0), g(p);
+      while (true) {
+        double w = coef;
+        for (int d = 0; d < p; ++d) {
+          w *= 0.5 * wl[d][c[d]];
+          g[d] = gl[d][c[d]];
+        }
+        sum_k.push_back(key_of(g));
+        sum_w.push_back(w);
+        int d = p - 1;
+        while (d >= 0 && ++c[d] == static_cast<int>(gl[d].size())) c[d--] = 0;
+        if (d < 0) break;
+      }
+    }
+    int d = p - 1;
+    while (d >= 0 && ++l[d] > L + 1) l[d--] = 1;
+    if (d < 0) break;
+  }
+  // merge by key
+  std::vector<size_t> ord(sum_k.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+    return sum_k[a] != sum_k[b] ? sum_k[a] < sum_k[b] : a < b;
+  });
+  nodes.clear();
+  wts.clear();
+  for (size_t i = 0; i < ord.size();) {
+    const long long k = sum_k[ord[i]];
+    double w = 0.0;
+    size_t j = i;
+    for (; j < ord.size() && sum_k[ord[j]] == k; ++j) w += sum_w[ord[j]];
+    long long r = k;
+    std::vector<double> xn(p);
+    for (int d = p - 1; d >= 0; --d) {
+      xn[d] = xf[static_cast<size_t>(r % fine)];
+      r /= fine;
+    }
+    nodes.insert(nodes.end(), xn.begin(), xn.end());
+    wts.push_back(w);
+    i = j;
+  }
+  return static_cast<int>(wts.size());
+}
+
+// Quadrature rules for xi ~ U(-1,1)^p selected by the problem: 0 tensor
+// Gauss-Legendre with `param` points per dimension, 1 tensor Clenshaw-Curtis
+// with `param` points per dimension, 2 Clenshaw-Curtis sparse grid of level
+// `param`.  Returns Q (0 for an unknown rule).
+inline int quadrature_rule(int rule, int p, int param, std::vector<double>& nodes,
+                           std::vector<double>& wts) {
+  if (rule == 0) return tensor_rule(p, param, nodes, wts);
+  if (rule == 1) {
+    std::vector<double> x, w;
+    clenshaw_curtis(param, x, w);
+    return tensor_from_1d(p, x, w, nodes, wts);
+  }
+  if (rule == 2) return cc_sparse_rule(p, param, nodes, wts);
+  return 0;
 }
 
 // Multi-indices with |i| <= degree, graded: total degree ascending, then the
