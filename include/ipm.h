@@ -145,6 +145,17 @@ typedef struct {
   const int *retard_degree;
   const double *retard_eps;
   int quad_rule;            /* IPM_QUAD_*; 0 (Gauss-Legendre) for the fields above */
+  /* Inexact-Hessian Newton (the outlook of Sec. 7: do not recompute the
+     Hessian at every iteration), for cells with more than 64 unknowns (the
+     workgroup kernel): 1 = each cell keeps the inverse of its last freshly
+     assembled Hessian in device memory (16T x 16T FP64 tiles, T = ceil(n/16),
+     about 74 KB per cell at n = 84) and takes later Newton steps, in this and
+     following time steps, as d = H_old^-1 grad L while each such step at
+     least halves the dual residual; otherwise the next iteration assembles
+     and inverts afresh.  The tau test is unchanged, so the dual still
+     converges to tau; results agree with exact Newton within the dual
+     tolerance, not bit for bit.  Fixed degrees only.  0 = exact Newton. */
+  int hessian_reuse;
 } ipm_problem;
 
 typedef struct {

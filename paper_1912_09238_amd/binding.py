@@ -50,6 +50,7 @@ class Problem(C.Structure):
         ("delta_lo", C.c_double), ("delta_hi", C.c_double),
         ("n_retard", C.c_int), ("retard_degree", C.POINTER(C.c_int)),
         ("retard_eps", C.POINTER(C.c_double)), ("quad_rule", C.c_int),
+        ("hessian_reuse", C.c_int),
     ]
 
 
@@ -178,6 +179,7 @@ def problem_struct(spec, keep):
     pb.one_shot = int(spec.get("one_shot", 0))
     pb.precision = PREC[spec.get("precision", "fp64")]
     pb.quad_rule = QUAD[spec.get("quad_rule", "gl")]
+    pb.hessian_reuse = int(spec.get("hessian_reuse", 0))
     pb.adapt = int(spec.get("adapt", 0))
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)

@@ -93,6 +93,12 @@ struct DualParams {
   const int* __restrict__ order;    // [order_len] cells of this class, ascending
   int order_len;
   int bcache;                       // precision form: B fragments cached in LDS
+  // inexact-Hessian Newton (workgroup kernel): per cell the inverse Hessian
+  // of its last fresh assembly, [cells][T*T][256] tiles, and a valid flag;
+  // null: exact Newton
+  double* __restrict__ hinv;
+  unsigned char* __restrict__ hinv_ok;
+  long long hinv_stride;            // doubles per cell in hinv
 };
 
 // ---------------------------------------------------------------- helpers

@@ -24,7 +24,16 @@
 //     column entries of its rows (multipliers) and, by symmetry of the
 //     trailing Schur complement, of its columns (the pivot row).  Only
 //     columns right of the pivot are updated: the eliminated pivot rows above
-//     are no longer symmetric with their columns.
+//     are no longer symmetric with their columns;
+//   - inexact-Hessian Newton (hinv set; the outlook of Sec. 7 on not
+//     recomputing the Hessian): a fresh assembly is inverted in place by
+//     Gauss-Jordan (both the pivot row and the pivot column are published,
+//     as the partly inverted matrix is not symmetric), the inverse's tiles
+//     are kept in HBM, and later Newton iterations of the cell, in this and
+//     in following steps, take d = H_old^-1 g from them while each such
+//     iteration at least halves the dual residual; otherwise the next
+//     iteration assembles and inverts afresh.  The tau test stays exact, so
+//     the iteration stops at the same FP64 tolerance.
 #pragma once
 
 #include "dual.hpp"
@@ -36,12 +45,15 @@ struct BigCfg {
   static_assert(16 % M == 0, "tile variables need M | 16");
   static constexpr int NPB = 16 * T;  // unknowns incl. identity padding
   static constexpr int NJ = M * (M + 1) / 2;
+  // inexact-Hessian Newton: right-hand side [NPB] and row partial sums
+  // [16][NPB] of the product with the stored inverse, after the rest
+  __host__ __device__ static size_t reuse_bytes() { return sizeof(double) * 17 * NPB; }
   __host__ __device__ static size_t lds_bytes(int Q, int kp, bool bcache = true) {
     // phi [Q][kp]; w [Q]; lam [NPB]; U [Q][M]; J [Q][NJ]; column [2][NPB];
     // pivot-row rhs [2]; reduction scratch [4][8]
     size_t b = sizeof(double) * (static_cast<size_t>(Q) * kp + Q + NPB +
                                  static_cast<size_t>(Q) * (M + NJ) + 2 * NPB + 2 + 32);
-    if (PREC == 1) {
+    if (PREC & 1) {
       // FP32 blocks [NJ][16 NT][16 NT] and BF16 hi/lo B fragments
       // [NT][QC][64 lanes][16], NT = ceil(N / 16), QC = ceil(Q / 32), N <= kp
       const size_t nt = (kp + 15) / 16, qc = (Q + 31) / 32;
@@ -118,7 +130,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
       lo[j] = l;
     }
   };
-  if constexpr (PREC == 1) {
+  if constexpr ((PREC & 1) != 0) {
     __syncthreads();  // phiL is complete
     if (P.bcache)
       for (int f = tid >> 6; f < NT * QC; f += 4) {
@@ -173,6 +185,36 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   if (ok) res = gradient();
   else status |= kStRealizability;
 
+  // inexact-Hessian Newton: LDS after the kernel's other areas
+  double* mvL = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) +
+                                          Cfg::lds_bytes(Q, kp, P.bcache != 0));
+  double* gS = mvL;                // [NPB] right-hand side
+  double* part = mvL + NPB;        // [16][NPB] row partial sums
+  double* rowb = part;             // [2][NPB] pivot rows during the inversion
+  bool chord = true;
+  // d (unknown tid) = sum_c Hinv[tid][c] g[c] from the register tiles, the
+  // column sums taken in a fixed order
+  auto inverse_times = [&](const double (&A)[T][T], double gv) -> double {
+    if (tid < NPB) gS[tid] = row_live ? gv : 0.0;
+    __syncthreads();
+    double gc[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) gc[j] = gS[tc + 16 * j];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < T; ++j) s = fma(A[i][j], gc[j], s);
+      part[tc * NPB + tr + 16 * i] = s;
+    }
+    __syncthreads();
+    double dv = 0.0;
+    if (tid < NPB)
+      for (int c = 0; c < 16; ++c) dv += part[c * NPB + tid];
+    __syncthreads();
+    return row_live ? dv : 0.0;
+  };
+
   while (ok) {
     if (!(res == res) || res > 1e300) {
       status |= kStNonfinite;
@@ -185,9 +227,21 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
         break;
       }
     }
-    // ---- Hessian tiles
+    // ---- inexact-Hessian Newton: the stored inverse while it contracts
+    constexpr bool reuse = (PREC & 2) != 0;  // inexact-Hessian variant
+    const bool stale = reuse && chord && P.hinv_ok[cell];  // uniform
+    double d = 0.0;
     double H[T][T];
-    if constexpr (PREC == 1) {
+    double* Hc = reuse ? P.hinv + static_cast<size_t>(cell) * P.hinv_stride : nullptr;
+    if (stale) {
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) H[i][j] = Hc[(i * T + j) * 256 + tid];
+      d = inverse_times(H, g);
+    } else {
+    // ---- Hessian tiles
+    if constexpr ((PREC & 1) != 0) {
       // blocks H_ab[i][k] = sum_q w_q J_ab(q) phi_i(q) phi_k(q) on the MFMA
       // units: task (ab, I) builds the A fragments of row tile I once per
       // chunk of 32 nodes and runs all column tiles K
@@ -290,6 +344,54 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
           }
       }
     }
+    if constexpr (reuse) {
+      // ---- in-place Gauss-Jordan inversion H <- H^-1 (SPD, no pivoting)
+      int pd_ok = 1;
+#pragma unroll
+      for (int jb = 0; jb < T; ++jb) {
+        for (int kk = 0; kk < 16; ++kk) {
+          const int k = jb * 16 + kk;
+          if (k >= nc) break;  // uniform
+          double* cb = col + (k & 1) * NPB;          // pivot column
+          double* rw = rowb + (k & 1) * NPB;         // pivot row
+          if (tc == kk) {
+#pragma unroll
+            for (int i = 0; i < T; ++i) cb[tr + 16 * i] = H[i][jb];
+          }
+          if (tr == kk) {
+#pragma unroll
+            for (int j = 0; j < T; ++j) rw[tc + 16 * j] = H[jb][j];
+          }
+          __syncthreads();
+          const double piv = cb[k];
+          pd_ok &= piv > 0.0 ? 1 : 0;
+          const double rp = recip(piv);
+          double cr[T], rc[T];
+#pragma unroll
+          for (int i = 0; i < T; ++i) cr[i] = cb[tr + 16 * i] * rp;
+#pragma unroll
+          for (int j = 0; j < T; ++j) rc[j] = rw[tc + 16 * j];
+#pragma unroll
+          for (int i = 0; i < T; ++i)
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+              const int r = tr + 16 * i, c = tc + 16 * j;
+              const double upd = fma(-cr[i], rc[j], H[i][j]);
+              H[i][j] = (r == k) ? ((c == k) ? rp : rc[j] * rp) : ((c == k) ? -cr[i] : upd);
+            }
+        }
+      }
+      if (!pd_ok) {  // uniform: every thread read the same pivots
+        status |= kStCholesky;
+        break;
+      }
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int j = 0; j < T; ++j) Hc[(i * T + j) * 256 + tid] = H[i][j];
+      if (tid == 0) P.hinv_ok[cell] = 1;
+      d = inverse_times(H, g);
+    } else {
     // ---- Gauss-Jordan solve H d = g
     double x = g, dg = 1.0;
     int pd_ok = 1;
@@ -315,15 +417,16 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
           const int r = tr + 16 * i;
           f[i] = (r == k) ? 0.0 : cb[r] * rp;
         }
+        // column blocks before the pivot's are eliminated already
 #pragma unroll
-        for (int j = 0; j < T; ++j) {
+        for (int j = jb; j < T; ++j) {
           const int c = tc + 16 * j;
           pr[j] = (c > k) ? cb[c] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < T; ++i)
 #pragma unroll
-          for (int j = 0; j < T; ++j) H[i][j] = fma(-f[i], pr[j], H[i][j]);
+          for (int j = jb; j < T; ++j) H[i][j] = fma(-f[i], pr[j], H[i][j]);
         if (tid < NPB) {
           if (tid == k) dg = piv;
           else x = fma(-(cb[tid] * rp), gk, x);
@@ -334,7 +437,9 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
       status |= kStCholesky;
       break;
     }
-    const double d = row_live ? x * recip(dg) : 0.0;
+    d = row_live ? x * recip(dg) : 0.0;
+    }  // exact solve
+    }  // fresh Hessian
     // ---- step length
     const bool ls = !P.one_shot && res > 1e-6;
     double L0 = 0.0, slope = 0.0;
@@ -378,7 +483,10 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
       status |= kStRealizability;
       break;
     }
+    const double res_old = res;
     res = gradient();
+    // a step from the stored inverse must at least halve the residual
+    if (stale && !(res <= 0.5 * res_old)) chord = false;
     if (P.one_shot) break;
   }
 
@@ -422,7 +530,8 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   }
 }
 
-// two workgroups per CU for the precision form up to T = 6 (its per-cell
+// PREC bit 0: BF16-split MFMA Hessian; bit 1: inexact-Hessian Newton.
+// Two workgroups per CU for the precision form up to T = 6 (its per-cell
 // latency is the lower one, so the launch is occupancy bound); larger tiles
 // do not fit two wavefronts' registers
 template <int M, int T, int PREC = 0>

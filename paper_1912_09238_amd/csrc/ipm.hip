@@ -83,6 +83,11 @@ struct Problem {
   // adaptive: the update of a step writes the other parity's buffer)
   int8_t* d_cellN[2] = {nullptr, nullptr};
   double* d_ctp = nullptr;  // analytic SG flux: triple products [N][N][N]
+  // inexact-Hessian Newton (workgroup-kernel cells): stored inverse tiles
+  int hessian_reuse = 0;
+  double* d_hinv = nullptr;
+  unsigned char* d_hinv_ok = nullptr;
+  long long hinv_stride = 0;
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;    // device bytes allocated
@@ -210,21 +215,33 @@ DualFn big_fn(int T) {
   return nullptr;
 }
 
-template <int M>
+// prec bit 0: BF16-split MFMA Hessian; bit 1: inexact-Hessian Newton (both
+// for T >= 5 only)
+template <int M, int PR>
 DualFn big_fn_prec(int T) {
   switch (T) {
-    case 5: return newton_big_kernel<M, 5, 1>;
-    case 6: return newton_big_kernel<M, 6, 1>;
-    case 8: return newton_big_kernel<M, 8, 1>;
-    case 9: return newton_big_kernel<M, 9, 1>;
+    case 5: return newton_big_kernel<M, 5, PR>;
+    case 6: return newton_big_kernel<M, 6, PR>;
+    case 8: return newton_big_kernel<M, 8, PR>;
+    case 9: return newton_big_kernel<M, 9, PR>;
+  }
+  return nullptr;
+}
+
+template <int M>
+DualFn big_fn_any(int T, int prec) {
+  switch (prec) {
+    case 1: return big_fn_prec<M, 1>(T);
+    case 2: return big_fn_prec<M, 2>(T);
+    case 3: return big_fn_prec<M, 3>(T);
   }
   return nullptr;
 }
 
 DualFn pick_big(int M, int T, int prec = 0) {
-  if (prec == 1) {
-    if (M == 1) return big_fn_prec<1>(T);
-    if (M == 4) return big_fn_prec<4>(T);
+  if (prec != 0) {
+    if (M == 1) return big_fn_any<1>(T, prec);
+    if (M == 4) return big_fn_any<4>(T, prec);
     return nullptr;
   }
   if (M == 1) return big_fn<1>(T);
@@ -235,7 +252,7 @@ DualFn pick_big(int M, int T, int prec = 0) {
 size_t big_lds_bytes(int M, int T, int Q, int kp, int prec = 0, bool bcache = true) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
-    if (prec == 1) switch (T) {
+    if (prec & 1) switch (T) {  // the reuse bit adds its own area (see plan)
         case 5: return BigCfg<MM, 5, 1>::lds_bytes(Q, kp, bcache);
         case 6: return BigCfg<MM, 6, 1>::lds_bytes(Q, kp, bcache);
         case 8: return BigCfg<MM, 8, 1>::lds_bytes(Q, kp, bcache);
@@ -344,7 +361,7 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv, P->d_hinv_ok};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
@@ -383,7 +400,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
         return fail(ctx, IPM_E_ARG, "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
       D.T = class_tiles(c);
       D.NP = 16 * D.T;
-      D.prec = P.precision == IPM_PREC_BF16 ? 1 : 0;
+      D.prec = (P.precision == IPM_PREC_BF16 ? 1 : 0) | (P.hessian_reuse ? 2 : 0);
     } else {
       D.NP = 8 << c;
       P.kp = std::max(P.kp, dual_table_columns(P.M, D.NP));
@@ -427,10 +444,11 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     if (D.T > 0) {
       D.waves = 4;
       D.bcache = 1;
-      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true);
-      if (D.prec == 1 && D.lds > ctx->max_lds) {  // build the B fragments on the fly instead
+      const size_t extra = (D.prec & 2) ? sizeof(double) * 17 * 16 * D.T : 0;
+      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true) + extra;
+      if ((D.prec & 1) && D.lds > ctx->max_lds) {  // build the B fragments on the fly instead
         D.bcache = 0;
-        D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false);
+        D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false) + extra;
       }
     }
     if (D.lds > ctx->max_lds)
@@ -495,6 +513,9 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   d.dim = P.dim;
   d.ctrl = ctrl;
   d.parity = parity;
+  d.hinv = P.d_hinv;
+  d.hinv_ok = P.d_hinv_ok;
+  d.hinv_stride = P.hinv_stride;
   return d;
 }
 
@@ -654,12 +675,19 @@ template <int M>
 const void* newton_batched_fn(int NP, int T, int prec) {
   if (T > 0) {
     if constexpr (16 % M == 0) {
-      if (prec == 1) switch (T) {
-          case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5, 1>);
-          case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6, 1>);
-          case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8, 1>);
-          case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9, 1>);
+      auto by_t = [&](auto pr) -> const void* {
+        constexpr int PR = decltype(pr)::value;
+        switch (T) {
+          case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5, PR>);
+          case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6, PR>);
+          case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8, PR>);
+          case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9, PR>);
         }
+        return nullptr;
+      };
+      if (prec == 1) return by_t(std::integral_constant<int, 1>{});
+      if (prec == 2) return by_t(std::integral_constant<int, 2>{});
+      if (prec == 3) return by_t(std::integral_constant<int, 3>{});
       switch (T) {
         case 1: return reinterpret_cast<const void*>(newton_big_batched<M, 1>);
         case 2: return reinterpret_cast<const void*>(newton_big_batched<M, 2>);
@@ -979,8 +1007,8 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
   for (int M : {1, 4})
     for (int T : {1, 2, 4, 5, 6, 8, 9})
-      for (int prec : {0, 1}) {
-        if (prec == 1 && T < 5) continue;
+      for (int prec : {0, 1, 2, 3}) {
+        if (prec != 0 && T < 5) continue;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T, prec)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, big);
         (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T, prec),
@@ -1063,6 +1091,10 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
     if (pb->quad_rule != IPM_QUAD_GAUSS_LEGENDRE || pb->quad_per_dim < pb->degree + 1)
       return fail(ctx, IPM_E_ARG, "adaptivity needs the Gauss-Legendre rule with quad_per_dim >= degree + 1");
   }
+  if (pb->hessian_reuse != 0 && pb->hessian_reuse != 1)
+    return fail(ctx, IPM_E_ARG, "hessian_reuse must be 0 or 1");
+  if (pb->hessian_reuse && pb->adapt)
+    return fail(ctx, IPM_E_ARG, "hessian_reuse takes fixed degrees (adapt = 0)");
   if (pb->n_retard != 0) {
     if (!pb->adapt || !(pb->steady_eps > 0.0))
       return fail(ctx, IPM_E_ARG, "refinement retardation needs adapt = 1 and steady_eps > 0");
@@ -1153,7 +1185,10 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
          cells + 2 * (cells + static_cast<size_t>(kCls) * kSlots * 16) * sizeof(int) + cells * sizeof(int) +
          sizeof(StepCtrl) +
          (pb->adapt ? cells + static_cast<size_t>(pb->degree) * 2 * (cells + kSlots * 16) * sizeof(int)
-                    : 0);
+                    : 0) +
+         (pb->hessian_reuse && n > 64
+              ? cells * (1 + sizeof(double) * 256 * static_cast<size_t>((n + 15) / 16) * ((n + 15) / 16))
+              : 0);
 }
 
 ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
@@ -1229,6 +1264,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
   P.adapt = pb->adapt ? 1 : 0;
+  P.hessian_reuse = pb->hessian_reuse;
   P.min_degree = pb->min_degree;
   P.delta_lo = pb->delta_lo;
   P.delta_hi = pb->delta_hi;
@@ -1315,6 +1351,16 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   if (pb->n_retard > 0) ALLOC(P.d_retard, sizeof(Retard));
   if (P.flux == IPM_FLUX_SG_ANALYTIC)
     ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
+  if (P.hessian_reuse) {
+    int tmax = 0;
+    for (const DualClass& D : P.cls)
+      if (D.configured && (D.prec & 2)) tmax = std::max(tmax, D.T);
+    if (tmax > 0) {
+      P.hinv_stride = static_cast<long long>(tmax) * tmax * 256;
+      ALLOC(P.d_hinv, static_cast<size_t>(P.cells) * P.hinv_stride * sizeof(double));
+      ALLOC(P.d_hinv_ok, static_cast<size_t>(P.cells));
+    }
+  }
   if (P.uneven) ALLOC(P.d_cellN[0], static_cast<size_t>(P.cells));
   if (P.adapt) ALLOC(P.d_cellN[1], static_cast<size_t>(P.cells));
   else P.d_cellN[1] = P.d_cellN[0];
@@ -1340,6 +1386,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
                            hipMemcpyHostToDevice, s));
   }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  if (P.d_hinv_ok) CHK(hipMemsetAsync(P.d_hinv_ok, 0, static_cast<size_t>(P.cells), s));
   std::vector<double> ctp;
   if (P.d_ctp) {
     // App. A: C_i = <phi phi^T phi_i>; the integrands have degree <= 3M, so a
