@@ -97,8 +97,9 @@ struct DualParams {
   // of its last fresh assembly, [cells][T*T][256] tiles, and a valid flag;
   // null: exact Newton
   double* __restrict__ hinv;
-  unsigned char* __restrict__ hinv_ok;
-  long long hinv_stride;            // doubles per cell in hinv
+  unsigned char* __restrict__ hinv_ok;      // [cells]
+  long long hinv_stride;                    // doubles per cell in hinv
+  const int* __restrict__ hinv_slot;        // [cells] slot in hinv (null: the cell index)
 };
 
 // ---------------------------------------------------------------- helpers

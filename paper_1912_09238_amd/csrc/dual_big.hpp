@@ -185,9 +185,13 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   if (ok) res = gradient();
   else status |= kStRealizability;
 
-  // inexact-Hessian Newton: LDS after the kernel's other areas
-  double* mvL = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) +
-                                          Cfg::lds_bytes(Q, kp, P.bcache != 0));
+  // inexact-Hessian Newton: LDS after the kernel's other areas, or, with the
+  // MFMA Hessian, the FP32 block area, which is free once the tiles are
+  // gathered
+  double* mvL = ((PREC & 1) != 0)
+                    ? reinterpret_cast<double*>(Hb)
+                    : reinterpret_cast<double*>(reinterpret_cast<char*>(smem) +
+                                                Cfg::lds_bytes(Q, kp, P.bcache != 0));
   double* gS = mvL;                // [NPB] right-hand side
   double* part = mvL + NPB;        // [16][NPB] row partial sums
   double* rowb = part;             // [2][NPB] pivot rows during the inversion
@@ -232,7 +236,9 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     const bool stale = reuse && chord && P.hinv_ok[cell];  // uniform
     double d = 0.0;
     double H[T][T];
-    double* Hc = reuse ? P.hinv + static_cast<size_t>(cell) * P.hinv_stride : nullptr;
+    double* Hc = reuse ? P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) *
+                                      P.hinv_stride
+                       : nullptr;
     if (stale) {
 #pragma unroll
       for (int i = 0; i < T; ++i)
@@ -302,6 +308,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
                         ? static_cast<double>(Hb[(static_cast<size_t>(ab) * S16 + r / M) * S16 + c / M])
                         : (r == c ? 1.0 : 0.0);
         }
+      if constexpr (reuse) __syncthreads();  // the inversion reuses the block area
     } else {
 #pragma unroll
       for (int i = 0; i < T; ++i)

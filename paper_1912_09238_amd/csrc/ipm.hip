@@ -46,6 +46,7 @@ struct DualClass {
   int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
   int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
   bool merged = false;      // its cells go to the lists of a larger class
+  double* d_hinv = nullptr; // inexact-Hessian Newton: inverse tiles of the class's cells
 };
 
 // Problems up to this many cells are latency bound: one Newton launch for
@@ -85,9 +86,15 @@ struct Problem {
   double* d_ctp = nullptr;  // analytic SG flux: triple products [N][N][N]
   // inexact-Hessian Newton (workgroup-kernel cells): stored inverse tiles
   int hessian_reuse = 0;
-  double* d_hinv = nullptr;
-  unsigned char* d_hinv_ok = nullptr;
-  long long hinv_stride = 0;
+  unsigned char* d_hinv_ok = nullptr;  // [cells] stored inverse valid
+  int* d_hinv_slot = nullptr;          // [cells] slot within the class's tiles
+  // the class's tiles and size (set per launch)
+  void set_hinv(DualParams& d, const DualClass& D) const {
+    d.hinv = D.d_hinv;
+    d.hinv_ok = d_hinv_ok;
+    d.hinv_stride = static_cast<long long>(D.T) * D.T * 256;
+    d.hinv_slot = d_hinv_slot;
+  }
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
   size_t bytes = 0;    // device bytes allocated
@@ -361,13 +368,14 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv, P->d_hinv_ok};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv_ok, P->d_hinv_slot};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
   for (DualClass& c : P->cls) {
     if (c.d_lists) (void)hipFree(c.d_lists);
     if (c.d_order) (void)hipFree(c.d_order);
+    if (c.d_hinv) (void)hipFree(c.d_hinv);
   }
 }
 
@@ -427,16 +435,24 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     DualClass& D = P.cls[c];
     if (!D.configured) continue;
     if (D.T == 0) {
+      // wavefronts per block: the most wavefronts per CU that LDS allows
+      // (160 KiB per CU); ties go to the larger block
+      auto per_cu = [&](int w) {
+        const size_t b = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, w);
+        return b > ctx->max_lds ? 0 : w * static_cast<int>(std::min<size_t>(4, (160 * 1024) / b));
+      };
       D.waves = 4;
-      while (D.waves > 1 && dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves) > 64 * 1024) D.waves >>= 1;
+      for (int w : {2, 1})
+        if (per_cu(w) > per_cu(D.waves)) D.waves = w;
       auto tw = ctx->tuned_waves.find(tune_key(P, D));
       if (tw != ctx->tuned_waves.end() &&
           dual_lds_bytes(P.M, D.NP, P.Q, P.kp, tw->second) <= ctx->max_lds)
         D.waves = tw->second;
       D.lds = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves);
-      // many nodes: the per-cell node buffers of a wavefront's cells do not
-      // fit, so the class runs on the workgroup-per-cell kernel
-      if (D.lds > ctx->max_lds && 16 % P.M == 0) {
+      // many nodes: the per-cell node buffers of a wavefront's cells leave
+      // fewer than two wavefronts per CU (or do not fit), so the class runs
+      // on the workgroup-per-cell kernel
+      if (per_cu(D.waves) < 2 && 16 % P.M == 0) {
         D.T = std::max(1, D.NP / 16);
         D.NP = 16 * D.T;
       }
@@ -444,7 +460,9 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     if (D.T > 0) {
       D.waves = 4;
       D.bcache = 1;
-      const size_t extra = (D.prec & 2) ? sizeof(double) * 17 * 16 * D.T : 0;
+      // the inexact-Hessian areas (17 x 16T doubles) live in the MFMA block
+      // area when there is one
+      const size_t extra = ((D.prec & 2) && !(D.prec & 1)) ? sizeof(double) * 17 * 16 * D.T : 0;
       D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true) + extra;
       if ((D.prec & 1) && D.lds > ctx->max_lds) {  // build the B fragments on the fly instead
         D.bcache = 0;
@@ -513,9 +531,6 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   d.dim = P.dim;
   d.ctrl = ctrl;
   d.parity = parity;
-  d.hinv = P.d_hinv;
-  d.hinv_ok = P.d_hinv_ok;
-  d.hinv_stride = P.hinv_stride;
   return d;
 }
 
@@ -546,8 +561,12 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
   }
   if (items == 0) return IPM_OK;
+  // the inverse tiles belong to the problem's cells: the Dirichlet ghosts'
+  // set-up runs the exact-Newton variant
+  const int prec = ghost_cells >= 0 ? (D.prec & 1) : D.prec;
+  if (prec & 2) P.set_hinv(d, D);
   if (D.T > 0) {
-    DualFn fn = pick_big(P.M, D.T, D.prec);
+    DualFn fn = pick_big(P.M, D.T, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     hipLaunchKernelGGL(fn, dim3(items), dim3(256), D.lds, ctx->stream, d);
   } else {
@@ -777,6 +796,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         dc.reset_next = first ? 1 : 0;
         first = false;
         dc.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+        if (D.prec & 2) P.set_hinv(dc, D);
         int items;
         if (P.lists()) {
           dc.lists = D.d_lists + static_cast<size_t>(parity) * kSlots * D.cap;
@@ -1173,6 +1193,20 @@ ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double* Phi, int
   return IPM_OK;
 }
 
+// inverse tiles of the inexact-Hessian Newton: cells with more than 64
+// unknowns, 16T x 16T doubles each (T of their size class), plus flags/slots
+static size_t reuse_bytes(const ipm_problem* pb, int M, size_t cells) {
+  size_t b = cells * (1 + sizeof(int));
+  for (size_t c = 0; c < cells; ++c) {
+    const int dg = pb->cell_degree ? pb->cell_degree[c] : pb->degree;
+    const int n = M * binom_basis(pb->p, dg);
+    if (n <= 64) continue;
+    const int T = class_tiles(size_class(n));
+    b += sizeof(double) * 256 * static_cast<size_t>(T) * T;
+  }
+  return b;
+}
+
 size_t ipm_problem_footprint(const ipm_problem* pb) {
   if (!pb) return 0;
   const int M = components(pb->equation);
@@ -1186,9 +1220,7 @@ size_t ipm_problem_footprint(const ipm_problem* pb) {
          sizeof(StepCtrl) +
          (pb->adapt ? cells + static_cast<size_t>(pb->degree) * 2 * (cells + kSlots * 16) * sizeof(int)
                     : 0) +
-         (pb->hessian_reuse && n > 64
-              ? cells * (1 + sizeof(double) * 256 * static_cast<size_t>((n + 15) / 16) * ((n + 15) / 16))
-              : 0);
+         (pb->hessian_reuse ? reuse_bytes(pb, M, cells) : 0);
 }
 
 ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
@@ -1352,13 +1384,16 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   if (P.flux == IPM_FLUX_SG_ANALYTIC)
     ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
   if (P.hessian_reuse) {
-    int tmax = 0;
-    for (const DualClass& D : P.cls)
-      if (D.configured && (D.prec & 2)) tmax = std::max(tmax, D.T);
-    if (tmax > 0) {
-      P.hinv_stride = static_cast<long long>(tmax) * tmax * 256;
-      ALLOC(P.d_hinv, static_cast<size_t>(P.cells) * P.hinv_stride * sizeof(double));
+    // tiles for the cells of each inexact-Hessian class only
+    bool any = false;
+    for (DualClass& D : P.cls)
+      if (D.configured && (D.prec & 2) && D.order_len > 0) {
+        ALLOC(D.d_hinv, static_cast<size_t>(D.order_len) * D.T * D.T * 256 * sizeof(double));
+        any = true;
+      }
+    if (any) {
       ALLOC(P.d_hinv_ok, static_cast<size_t>(P.cells));
+      if (P.uneven) ALLOC(P.d_hinv_slot, static_cast<size_t>(P.cells) * sizeof(int));
     }
   }
   if (P.uneven) ALLOC(P.d_cellN[0], static_cast<size_t>(P.cells));
@@ -1387,6 +1422,14 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
   if (P.d_hinv_ok) CHK(hipMemsetAsync(P.d_hinv_ok, 0, static_cast<size_t>(P.cells), s));
+  std::vector<int> hslot;
+  if (P.d_hinv_slot) {  // a cell's slot: its position in its class's cell order
+    hslot.assign(P.cells, 0);
+    std::vector<int> seen(kCls, 0);
+    for (int c = 0; c < P.cells; ++c) hslot[c] = seen[cell_cls[c]]++;
+    CHK(hipMemcpyAsync(P.d_hinv_slot, hslot.data(), hslot.size() * sizeof(int),
+                       hipMemcpyHostToDevice, s));
+  }
   std::vector<double> ctp;
   if (P.d_ctp) {
     // App. A: C_i = <phi phi^T phi_i>; the integrands have degree <= 3M, so a

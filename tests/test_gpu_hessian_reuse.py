@@ -61,6 +61,54 @@ def test_reuse_three_uncertainties_140_unknowns(gpu_ctx, orc):
     _run(gpu_ctx, orc, spec, 6)
 
 
+def test_reuse_uneven_degrees(gpu_ctx, orc):
+    """Per-cell degrees 1..4: only the 80- and 140-unknown classes keep
+    inverse tiles, each cell in its class's slot."""
+    spec = W.bump2d(n=10, degree=4, qpd=5, p=3, v1_spread=0.2)
+    spec.update(ny=7, hessian_reuse=1)
+    cd = np.random.default_rng(11).integers(1, 5, size=70).astype(np.int8)
+    from paper_1912_09238_amd import binding
+    nodes, _ = binding.quadrature(3, 5)
+    _say("gpu case: hessian reuse, uneven degrees 1..4, p=3, 70 cells, 6 steps")
+    pid = gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes), cell_degree=cd)
+    info = gpu_ctx.step(pid, 6, wait=True)[0]
+    got = gpu_ctx.moments(pid)
+    gpu_ctx.release(pid)
+    ref = dict(spec)
+    ref.pop("hessian_reuse")
+    o = orc.Oracle(ref, ic_fn=lambda nd: W.ic_nodal(ref, nd), cell_degree=cd)
+    oinfo = o.step(6)
+    assert info["status"] == 0 and oinfo["status"] == 0
+    err = parity(got, o.moments())
+    _say("  parity %s" % np.array2string(err, precision=2))
+    assert np.all(err <= 1e-8), err
+
+
+def test_reuse_batched_equals_alone(gpu_ctx):
+    from paper_1912_09238_amd import binding
+    a = W.bump2d(n=12, degree=5, qpd=8, p=2)
+    a.update(ny=10, hessian_reuse=1, precision="bf16")
+    b = W.bump2d(n=8, degree=4, qpd=5, p=3, v1_spread=0.2)
+    b.update(ny=9, hessian_reuse=1)
+    specs = [a, b]
+    _say("gpu case: hessian reuse, two problems batched vs alone")
+
+    def make(spec):
+        nodes, _ = binding.quadrature(spec["p"], spec["quad_per_dim"])
+        return gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+    alone = []
+    for spec in specs:
+        pid = make(spec)
+        gpu_ctx.step(pid, 7, wait=True)
+        alone.append(gpu_ctx.moments(pid))
+        gpu_ctx.release(pid)
+    ids = [make(spec) for spec in specs]
+    gpu_ctx.step(ids, 7, wait=True)
+    for k, pid in enumerate(ids):
+        assert np.array_equal(gpu_ctx.moments(pid), alone[k]), k
+        gpu_ctx.release(pid)
+
+
 def test_reuse_needs_fixed_degrees(gpu_ctx):
     from paper_1912_09238_amd import binding
     spec = W.bump2d(n=8, degree=5, qpd=8, p=2)
