@@ -268,11 +268,53 @@ def serve_form(args):
     t0 = time.perf_counter()
     res = ctx.serve(reqs, steps_per_round=args.round, max_active=args.max_active, moments=False)
     wall = time.perf_counter() - t0
-    ctx.close()
     assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:3]
     lat = np.array([r["latency"] for r in res])
     work = sum(r["steps"] * rq["spec"]["nx"] for r, rq in zip(res, reqs))
     makespan = max(r["finished"] for r in res)
+    # 2D requests (21 unknowns per variable, 84 per cell), where the precision
+    # form applies: the same stream served in the FP64 form and in the
+    # mixed-precision form (BF16 Hessian + inverse reuse), at an open-loop
+    # rate the GPU keeps up with and at a rate that saturates it; moments of
+    # each request compared between the forms
+    two_d = {}
+    n2, _ = binding.quadrature(2, 8)
+    for rate in args.rate_2d:
+        stream = W.request_stream_2d(rate=rate, duration=args.duration)
+        row, moms = {}, {}
+        for form, kw in (("fp64", {}), ("mixed", dict(precision="bf16", hessian_reuse=1))):
+            rq2 = [{"spec": dict(sp, **kw), "arrival": sp["arrival"],
+                    "ic_nodal": W.ic_nodal(sp, n2)} for sp in stream]
+            r2 = ctx.serve(rq2, steps_per_round=args.round, max_active=args.max_active,
+                           moments=True)
+            assert all(r["status"] == 0 for r in r2), [r for r in r2 if r["status"]][:3]
+            l2 = np.array([r["latency"] for r in r2])
+            w2 = sum(r["steps"] * sp["nx"] * sp["ny"] for r, sp in zip(r2, stream))
+            m2 = max(r["finished"] for r in r2)
+            moms[form] = [r["moments"] for r in r2]
+            row[form] = {"served_cell_updates_per_s": w2 / m2, "makespan_s": m2,
+                         "latency_s": {"p50": float(np.percentile(l2, 50)),
+                                       "p99": float(np.percentile(l2, 99))}}
+            row["offered_cell_updates_per_s"] = w2 / args.duration
+            print("serve form, 2D at %g/s %s: %.4g cell-updates/s, p50 %.4f s, p99 %.4f s" % (
+                rate, form, w2 / m2, row[form]["latency_s"]["p50"],
+                row[form]["latency_s"]["p99"]), file=sys.stderr, flush=True)
+        pairs = list(zip(moms["mixed"], moms["fp64"]))
+        num_e = sum(np.abs(a[:, :, 0] - b[:, :, 0]).sum() for a, b in pairs)
+        den_e = sum(np.abs(b[:, :, 0]).sum() for _, b in pairs)
+        num_v = sum(np.abs((a[:, :, 1:] ** 2).sum(2) - (b[:, :, 1:] ** 2).sum(2)).sum()
+                    for a, b in pairs)
+        den_v = sum((b[:, :, 1:] ** 2).sum() for _, b in pairs)
+        row["requests"] = len(stream)
+        row["mixed_rel_l1_vs_fp64"] = {"E": float(num_e / den_e), "Var": float(num_v / den_v)}
+        row["speedup_served"] = (row["mixed"]["served_cell_updates_per_s"] /
+                                 row["fp64"]["served_cell_updates_per_s"])
+        row["p50_ratio_fp64_over_mixed"] = (row["fp64"]["latency_s"]["p50"] /
+                                            row["mixed"]["latency_s"]["p50"])
+        row["p99_ratio_fp64_over_mixed"] = (row["fp64"]["latency_s"]["p99"] /
+                                            row["mixed"]["latency_s"]["p99"])
+        two_d["poisson%g" % rate] = row
+    ctx.close()
     return {
         "metric": METRIC, "value": work / makespan, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -285,6 +327,7 @@ def serve_form(args):
                       "max": float(lat.max())},
         "offered_cell_updates_per_s": work / args.duration,
         "served_cell_updates_per_s": work / makespan, "makespan_s": makespan, "wall_s": wall,
+        "requests_2d_fp64_vs_mixed": two_d,
     }
 
 
@@ -528,6 +571,7 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rate-2d", type=float, nargs="+", default=[40.0, 400.0])
     ap.add_argument("--duration", type=float, default=1.0)
     ap.add_argument("--round", type=int, default=8)
     ap.add_argument("--max-active", type=int, default=64)

@@ -89,3 +89,22 @@ def test_admission_by_hbm_footprint():
         t = r["admitted"]
         live = [j for j, s in enumerate(res[:-1]) if s["admitted"] <= t < s["finished"]]
         assert sum(fps[j] for j in live) <= budget, (k, live)
+
+
+def test_served_mixed_precision_2d_equals_alone(gpu_ctx):
+    """2D requests in the mixed-precision form (BF16 Hessian + inverse
+    reuse): served in a mix, each equals the same problem stepped alone."""
+    from paper_1912_09238_amd import binding
+    nodes, _ = binding.quadrature(2, 8)
+    reqs = []
+    for k, spec in enumerate(W.request_stream_2d(rate=2000.0, duration=0.003, seed=7)[:5]):
+        spec = dict(spec, nx=spec["nx"] // 2, ny=spec["ny"] // 2, t_end=0.01,
+                    precision="bf16", hessian_reuse=1)
+        reqs.append({"spec": spec, "arrival": spec["arrival"], "ic_nodal": W.ic_nodal(spec, nodes)})
+    _say("gpu case: serve %d 2D mixed-precision requests, rounds of 2 steps" % len(reqs))
+    res = gpu_ctx.serve(reqs, steps_per_round=2, max_active=3)
+    for k, (rq, r) in enumerate(zip(reqs, res)):
+        assert r["status"] == 0, (k, r)
+        info, mom = _alone(gpu_ctx, rq)
+        assert r["steps"] == info["steps"]
+        assert np.array_equal(r["moments"], mom), k
