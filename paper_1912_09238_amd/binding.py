@@ -51,6 +51,7 @@ class Problem(C.Structure):
         ("n_retard", C.c_int), ("retard_degree", C.POINTER(C.c_int)),
         ("retard_eps", C.POINTER(C.c_double)), ("quad_rule", C.c_int),
         ("hessian_reuse", C.c_int),
+        ("reuse_theta", C.c_double),
     ]
 
 
@@ -180,6 +181,7 @@ def problem_struct(spec, keep):
     pb.precision = PREC[spec.get("precision", "fp64")]
     pb.quad_rule = QUAD[spec.get("quad_rule", "gl")]
     pb.hessian_reuse = int(spec.get("hessian_reuse", 0))
+    pb.reuse_theta = float(spec.get("reuse_theta", 0.0))
     pb.adapt = int(spec.get("adapt", 0))
     pb.min_degree = spec.get("min_degree", 1)
     pb.delta_lo = spec.get("delta_lo", 0.0)

@@ -1,23 +1,44 @@
-"""Build libipm.so for gfx950 with hipcc (in-tree)."""
+"""Build libipm.so for gfx950 with hipcc (in-tree).
+
+The library is split into translation units that compile in parallel: the
+host runtime (ipm.hip) and one unit per kernel family and variable count
+(each kernel template is instantiated in exactly one unit)."""
+import concurrent.futures
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ipm.hip")
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libipm.so")
+UNITS = ["kernels_big_m4.hip", "kernels_big_m1.hip", "kernels_dual_m3.hip",
+         "kernels_dual_m4.hip", "kernels_dual_m1.hip", "kernels_update.hip", "ipm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
 
-def build(verbose=False):
-    cmd = [HIPCC] + FLAGS + [SRC, "-o", OUT + ".tmp"]
+def _compile(unit, verbose):
+    obj = os.path.join(BUILD, unit.replace(".hip", ".o"))
+    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, unit), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, cwd=HERE)
+    return obj
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(u, verbose), UNITS))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)

@@ -23,7 +23,16 @@
 //        so every row is updated from it, the right-hand side is eliminated
 //        along, and no back-substitution (no transposed access) is needed;
 //      - step length: Armijo backtracking on L when the dual residual
-//        exceeds 1e-6, else the full step; one-shot: one full step.
+//        exceeds 1e-6, else the full step; one-shot: one full step;
+//      - inexact-Hessian variant (PREC bit 1; the outlook of Sec. 7 on not
+//        recomputing the Hessian): a fresh Hessian is inverted in place by
+//        the symmetric sweep (the matrix stays symmetric, so the broadcast
+//        pivot column again serves as the pivot row), the rows of -H^-1 go
+//        to HBM, and later iterations of the cell, in this and following
+//        steps, take d = H_old^-1 g from them while each such step
+//        contracts the dual residual by a factor theta; otherwise the inverse is retired and the
+//        next iteration (one-shot: of the next pseudo-time step) assembles
+//        and inverts afresh.  The tau test is unchanged.
 // The dual, the nodal ansatz (read by the flux update) and the wave speeds
 // leave the kernels; the Hessian never touches HBM.  Statistics go to
 // per-block cumulative counters (plain stores) and to 64 atomic speed slots
@@ -93,13 +102,14 @@ struct DualParams {
   const int* __restrict__ order;    // [order_len] cells of this class, ascending
   int order_len;
   int bcache;                       // precision form: B fragments cached in LDS
-  // inexact-Hessian Newton (workgroup kernel): per cell the inverse Hessian
-  // of its last fresh assembly, [cells][T*T][256] tiles, and a valid flag;
-  // null: exact Newton
+  // inexact-Hessian Newton: per cell the inverse Hessian of its last fresh
+  // assembly (workgroup kernel: [T*T][256] tiles; small kernel: rows of
+  // -H^-1 as [NP][NP] by column), and a valid flag; null: exact Newton
   double* __restrict__ hinv;
   unsigned char* __restrict__ hinv_ok;      // [cells]
   long long hinv_stride;                    // doubles per cell in hinv
   const int* __restrict__ hinv_slot;        // [cells] slot in hinv (null: the cell index)
+  double reuse_theta;                       // a stale step must give res_new <= theta res_old
 };
 
 // ---------------------------------------------------------------- helpers
@@ -331,7 +341,7 @@ __device__ __forceinline__ void reset_next_step(const DualParams& P) {
     C->list_len[list_len_index(P.parity ^ 1, k / kSlots, k % kSlots)] = 0u;
 }
 
-template <int M, int NP>
+template <int M, int NP, int PREC = 0>
 __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) {
   using Cfg = NewtonCfg<M, NP>;
   constexpr int G = Cfg::G, CPW = Cfg::CPW, NJ = Cfg::NJ, R = Cfg::R;
@@ -431,6 +441,16 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
     if (ok) res = gradient();
     else status |= kStRealizability;
 
+    constexpr bool reuse = (PREC & 2) != 0;  // inexact-Hessian variant
+    bool chord = true;
+    // the cell's stored inverse is valid: read once, then kept in step with
+    // the flag this cell writes (no re-read of its own write)
+    bool have_inv = false;
+    if constexpr (reuse) have_inv = P.hinv_ok[cell] != 0;
+    double* Hc = nullptr;  // the cell's stored rows of -H^-1, [NP][NP] by column
+    if constexpr (reuse)
+      Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
+
     while (ok) {
       if (!(res == res) || res > 1e300) {
         status |= kStNonfinite;
@@ -443,145 +463,270 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           break;
         }
       }
-      // ---- Hessian rows in registers; identity beyond the nc unknowns
+      // ---- inexact-Hessian Newton: a step from the stored inverse while
+      // such steps contract, else a fresh Hessian (inverted and stored)
       double row[R][NP];
+      double d[R];
+      bool fresh = true;
+      if constexpr (reuse) {
+        if (chord && have_inv) {  // uniform in the group
+          fresh = false;
 #pragma unroll
-      for (int s = 0; s < R; ++s)
+          for (int s = 0; s < R; ++s)
 #pragma unroll
-        for (int c = 0; c < NP; ++c) row[s][c] = 0.0;
-      {
-        int aidx[R][M];
-        double live_f[R];
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-          live_f[s] = live[s] ? 1.0 : 0.0;
-#pragma unroll
-          for (int b = 0; b < M; ++b) aidx[s][b] = Packed<M>::idx(aa[s], b);
+            for (int c = 0; c < NP; ++c) row[s][c] = Hc[c * NP + ro[s]];
         }
-        for (int q = 0; q < Q; ++q) {
-          const double* Jq = JS + q * NJ;
-          double sb[R][M];
-#pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const double wi = wphiL[q * kp + ii[s]] * live_f[s];
-#pragma unroll
-            for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
-          }
-          const_dptr ph = phiC + q * kp;  // uniform: scalar loads
-#pragma unroll
-          for (int c = 0; c < NP; ++c) {
-            const double v = ph[c / M];
-#pragma unroll
-            for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < R; ++s)
-#pragma unroll
-          for (int c = 0; c < NP; ++c)
-            row[s][c] = (live[s] && c < nc) ? row[s][c] : (c == ro[s] ? 1.0 : 0.0);
       }
-      // ---- Gauss-Jordan solve H d = g without pivoting (H is SPD).  In the
-      // symmetric Schur complement the pivot row equals the pivot column, so
-      // a broadcast of the column serves all rows and the eliminated system
-      // needs no back-substitution.
-      double x[R], d[R];
-      int pd_ok = 1;
-      if constexpr (kDpp) {
-        // column entry j lives in lane j of the group; lanes 16..31 of a
-        // 32-lane group are reached through the swapped copy
-        auto halves = [&](double v, double& lo, double& hi) __attribute__((always_inline)) {
-          if constexpr (G == 32) {
-            group32_halves(v, lo, hi);
-          } else {
-            lo = v;
-            hi = v;
+      if (fresh) {
+        // ---- Hessian rows in registers; identity beyond the nc unknowns
+  #pragma unroll
+        for (int s = 0; s < R; ++s)
+  #pragma unroll
+          for (int c = 0; c < NP; ++c) row[s][c] = 0.0;
+        {
+          int aidx[R][M];
+          double live_f[R];
+  #pragma unroll
+          for (int s = 0; s < R; ++s) {
+            live_f[s] = live[s] ? 1.0 : 0.0;
+  #pragma unroll
+            for (int b = 0; b < M; ++b) aidx[s][b] = Packed<M>::idx(aa[s], b);
           }
-        };
-        double dg = 1.0, xv = g[0];
-        static_for<0, NP>([&](auto kc) __attribute__((always_inline)) {
-          constexpr int k = decltype(kc)::value;
-          if (k < kmax) {
-            double clo, chi, xlo, xhi;
-            halves(row[0][k], clo, chi);
-            halves(xv, xlo, xhi);
-            const double piv = (k < 16) ? row_bcast<k % 16>(clo) : row_bcast<k % 16>(chi);
-            const double gk = (k < 16) ? row_bcast<k % 16>(xlo) : row_bcast<k % 16>(xhi);
-            pd_ok &= piv > 0.0 ? 1 : 0;
-            if (r == k) dg = piv;
-            const double f = (r == k) ? 0.0 : row[0][k] * recip(piv);
-            const double negf = -f;
-            xv = fma(-f, gk, xv);
-            dpp_guard(clo, chi);
-            static_for<k + 1, NP>([&](auto jc) __attribute__((always_inline)) {
-              constexpr int j = decltype(jc)::value;
-              if constexpr (j == 16 && k + 1 < 16) dpp_guard(clo, chi);
-              fmac_row_bcast<j % 16>(row[0][j], (j < 16) ? clo : chi, negf);
+          for (int q = 0; q < Q; ++q) {
+            const double* Jq = JS + q * NJ;
+            double sb[R][M];
+  #pragma unroll
+            for (int s = 0; s < R; ++s) {
+              const double wi = wphiL[q * kp + ii[s]] * live_f[s];
+  #pragma unroll
+              for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
+            }
+            const_dptr ph = phiC + q * kp;  // uniform: scalar loads
+  #pragma unroll
+            for (int c = 0; c < NP; ++c) {
+              const double v = ph[c / M];
+  #pragma unroll
+              for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
+            }
+          }
+  #pragma unroll
+          for (int s = 0; s < R; ++s)
+  #pragma unroll
+            for (int c = 0; c < NP; ++c)
+              row[s][c] = (live[s] && c < nc) ? row[s][c] : (c == ro[s] ? 1.0 : 0.0);
+        }
+
+        if constexpr (reuse) {
+          // ---- in-place symmetric sweep: H <- -H^-1 (SPD, no pivoting).
+          // Step k: pivot p = h_kk; h_kk <- -1/p; row and column k divided by
+          // p; h_ij -= h_ik h_kj / p elsewhere.  The matrix stays symmetric,
+          // so the pivot row is the broadcast pivot column for every lane; the
+          // pivot lane scales its row by 1/p with the multiplier 1/p - 1
+          // against that column.
+          int pd_ok = 1;
+          if constexpr (kDpp) {
+            auto halves = [&](double v, double& lo, double& hi) __attribute__((always_inline)) {
+              if constexpr (G == 32) {
+                group32_halves(v, lo, hi);
+              } else {
+                lo = v;
+                hi = v;
+              }
+            };
+            static_for<0, NP>([&](auto kc) __attribute__((always_inline)) {
+              constexpr int k = decltype(kc)::value;
+              if (k < kmax) {
+                double clo, chi;
+                halves(row[0][k], clo, chi);
+                const double piv = (k < 16) ? row_bcast<k % 16>(clo) : row_bcast<k % 16>(chi);
+                pd_ok &= piv > 0.0 ? 1 : 0;
+                const double rp = recip(piv);
+                const double f = row[0][k] * rp;
+                const double mul = (r == k) ? rp - 1.0 : -f;
+                dpp_guard(clo, chi);
+                static_for<0, NP>([&](auto jc) __attribute__((always_inline)) {
+                  constexpr int j = decltype(jc)::value;
+                  if constexpr (j == 16) dpp_guard(clo, chi);
+                  if constexpr (j != k)
+                    fmac_row_bcast<j % 16>(row[0][j], (j < 16) ? clo : chi, mul);
+                });
+                row[0][k] = (r == k) ? -rp : f;
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            });
+          } else {
+#pragma unroll
+            for (int s = 0; s < R; ++s) cA[ro[s]] = row[s][0];
+            wave_sync();
+            // compile-time steps and columns: every register index static
+            static_for<0, NP>([&](auto kc) __attribute__((always_inline)) {
+              constexpr int k = decltype(kc)::value;
+              if (k < nc) {
+                const double* A = cA + (k & 1) * NP;
+                double* An = cA + ((k + 1) & 1) * NP;
+                const double piv = A[k];
+                pd_ok &= piv > 0.0 ? 1 : 0;
+                const double rp = recip(piv);
+                double f[R], mul[R];
+#pragma unroll
+                for (int s = 0; s < R; ++s) {
+                  f[s] = row[s][k] * rp;
+                  mul[s] = (ro[s] == k) ? rp - 1.0 : -f[s];
+                }
+                if constexpr (k + 1 < NP) {  // publish the next column first
+                  const double c1 = A[k + 1];
+#pragma unroll
+                  for (int s = 0; s < R; ++s) {
+                    row[s][k + 1] = fma(mul[s], c1, row[s][k + 1]);
+                    An[ro[s]] = row[s][k + 1];
+                  }
+                }
+                // the column read entry by entry (a whole column in registers
+                // beside the whole row would spill)
+                static_for<0, NP>([&](auto jc) __attribute__((always_inline)) {
+                  constexpr int j = decltype(jc)::value;
+                  if constexpr (j != k && j != k + 1) {
+                    const double cj = A[j];
+#pragma unroll
+                    for (int s = 0; s < R; ++s) row[s][j] = fma(mul[s], cj, row[s][j]);
+                  }
+                });
+#pragma unroll
+                for (int s = 0; s < R; ++s) row[s][k] = (ro[s] == k) ? -rp : f[s];
+                wave_sync();
+              }
             });
           }
-          // one step at a time: interleaving steps keeps every step's
-          // multipliers and broadcasts live at once
-          __builtin_amdgcn_sched_barrier(0);
-        });
-        if (!group_all(pd_ok)) {
-          status |= kStCholesky;
-          break;
-        }
-        x[0] = xv;
-        d[0] = live[0] ? xv * recip(dg) : 0.0;
-      } else {
-        // LDS broadcast: the step reads the whole column in one batch,
-        // updates and publishes the next column first, then the rest of the
-        // row while that write lands
+          if (!group_all(pd_ok)) {
+            status |= kStCholesky;
+            break;
+          }
+#pragma unroll
+          for (int s = 0; s < R; ++s)
+#pragma unroll
+            for (int c = 0; c < NP; ++c) Hc[c * NP + ro[s]] = row[s][c];
+          if (r == 0) P.hinv_ok[cell] = 1;
+          have_inv = true;
+        } else {
+          // ---- Gauss-Jordan solve H d = g without pivoting (H is SPD).  In the
+          // symmetric Schur complement the pivot row equals the pivot column, so
+          // a broadcast of the column serves all rows and the eliminated system
+          // needs no back-substitution.
+          double x[R];
+          int pd_ok = 1;
+          if constexpr (kDpp) {
+            // column entry j lives in lane j of the group; lanes 16..31 of a
+            // 32-lane group are reached through the swapped copy
+            auto halves = [&](double v, double& lo, double& hi) __attribute__((always_inline)) {
+              if constexpr (G == 32) {
+                group32_halves(v, lo, hi);
+              } else {
+                lo = v;
+                hi = v;
+              }
+            };
+            double dg = 1.0, xv = g[0];
+            static_for<0, NP>([&](auto kc) __attribute__((always_inline)) {
+              constexpr int k = decltype(kc)::value;
+              if (k < kmax) {
+                double clo, chi, xlo, xhi;
+                halves(row[0][k], clo, chi);
+                halves(xv, xlo, xhi);
+                const double piv = (k < 16) ? row_bcast<k % 16>(clo) : row_bcast<k % 16>(chi);
+                const double gk = (k < 16) ? row_bcast<k % 16>(xlo) : row_bcast<k % 16>(xhi);
+                pd_ok &= piv > 0.0 ? 1 : 0;
+                if (r == k) dg = piv;
+                const double f = (r == k) ? 0.0 : row[0][k] * recip(piv);
+                const double negf = -f;
+                xv = fma(-f, gk, xv);
+                dpp_guard(clo, chi);
+                static_for<k + 1, NP>([&](auto jc) __attribute__((always_inline)) {
+                  constexpr int j = decltype(jc)::value;
+                  if constexpr (j == 16 && k + 1 < 16) dpp_guard(clo, chi);
+                  fmac_row_bcast<j % 16>(row[0][j], (j < 16) ? clo : chi, negf);
+                });
+              }
+              // one step at a time: interleaving steps keeps every step's
+              // multipliers and broadcasts live at once
+              __builtin_amdgcn_sched_barrier(0);
+            });
+            if (!group_all(pd_ok)) {
+              status |= kStCholesky;
+              break;
+            }
+            x[0] = xv;
+            d[0] = live[0] ? xv * recip(dg) : 0.0;
+          } else {
+            // LDS broadcast: the step reads the whole column in one batch,
+            // updates and publishes the next column first, then the rest of the
+            // row while that write lands
+    #pragma unroll
+            for (int s = 0; s < R; ++s) {
+              x[s] = g[s];
+              cA[ro[s]] = row[s][0];
+            }
+            if (r == 0) cX[0] = x[0];
+            wave_sync();
+    #pragma unroll
+            for (int k = 0; k < NP; ++k) {
+              // steps beyond the cell's unknowns would only touch the identity block
+              if (k < nc) {
+                const double* A = cA + (k & 1) * NP;
+                double* An = cA + ((k + 1) & 1) * NP;
+                double col[NP];
+    #pragma unroll
+                for (int j = k; j < NP; ++j) col[j] = A[j];
+                const double gk = cX[k & 1];
+                const double piv = col[k];
+                pd_ok &= piv > 0.0 ? 1 : 0;
+                if (r == k % G) cP[k] = piv;
+                const double rp = recip(piv);
+                double f[R];
+    #pragma unroll
+                for (int s = 0; s < R; ++s) {
+                  f[s] = (ro[s] == k) ? 0.0 : row[s][k] * rp;
+                  x[s] = fma(-f[s], gk, x[s]);
+                }
+                if (k + 1 < NP) {
+    #pragma unroll
+                  for (int s = 0; s < R; ++s) {
+                    row[s][k + 1] = fma(-f[s], col[k + 1], row[s][k + 1]);
+                    An[ro[s]] = row[s][k + 1];
+                  }
+                  if (r == (k + 1) % G) cX[(k + 1) & 1] = x[(k + 1) / G];
+                }
+    #pragma unroll
+                for (int j = k + 2; j < NP; ++j)
+    #pragma unroll
+                  for (int s = 0; s < R; ++s) row[s][j] = fma(-f[s], col[j], row[s][j]);
+                wave_sync();
+              }
+            }
+            if (!group_all(pd_ok)) {
+              status |= kStCholesky;
+              break;
+            }
+            wave_sync();
+    #pragma unroll
+            for (int s = 0; s < R; ++s) d[s] = live[s] ? x[s] * recip(cP[ro[s]]) : 0.0;
+          }
+
+        }  // exact solve
+      }  // fresh Hessian
+      if constexpr (reuse) {
+        // d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area
+        // (free until the line search writes the trial dual)
+#pragma unroll
+        for (int s = 0; s < R; ++s) lamS[ro[s]] = g[s];
+        wave_sync();
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          x[s] = g[s];
-          cA[ro[s]] = row[s][0];
-        }
-        if (r == 0) cX[0] = x[0];
-        wave_sync();
+          double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          // steps beyond the cell's unknowns would only touch the identity block
-          if (k < nc) {
-            const double* A = cA + (k & 1) * NP;
-            double* An = cA + ((k + 1) & 1) * NP;
-            double col[NP];
-#pragma unroll
-            for (int j = k; j < NP; ++j) col[j] = A[j];
-            const double gk = cX[k & 1];
-            const double piv = col[k];
-            pd_ok &= piv > 0.0 ? 1 : 0;
-            if (r == k % G) cP[k] = piv;
-            const double rp = recip(piv);
-            double f[R];
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-              f[s] = (ro[s] == k) ? 0.0 : row[s][k] * rp;
-              x[s] = fma(-f[s], gk, x[s]);
-            }
-            if (k + 1 < NP) {
-#pragma unroll
-              for (int s = 0; s < R; ++s) {
-                row[s][k + 1] = fma(-f[s], col[k + 1], row[s][k + 1]);
-                An[ro[s]] = row[s][k + 1];
-              }
-              if (r == (k + 1) % G) cX[(k + 1) & 1] = x[(k + 1) / G];
-            }
-#pragma unroll
-            for (int j = k + 2; j < NP; ++j)
-#pragma unroll
-              for (int s = 0; s < R; ++s) row[s][j] = fma(-f[s], col[j], row[s][j]);
-            wave_sync();
-          }
-        }
-        if (!group_all(pd_ok)) {
-          status |= kStCholesky;
-          break;
+          for (int j = 0; j < NP; ++j) acc = fma(row[s][j], lamS[j], acc);
+          d[s] = live[s] ? -acc : 0.0;
         }
         wave_sync();
-#pragma unroll
-        for (int s = 0; s < R; ++s) d[s] = live[s] ? x[s] * recip(cP[ro[s]]) : 0.0;
       }
       // ---- step length
       const bool ls = !P.one_shot && res > 1e-6;
@@ -638,7 +783,16 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
         status |= kStRealizability;
         break;
       }
+      const double res_old = res;
       res = gradient();
+      // a step from the stored inverse must contract the residual by
+      // theta, else the inverse is retired: the cell's next iteration, in this or a
+      // later step (one-shot: the next pseudo-time step), assembles afresh
+      if (!fresh && !(res <= P.reuse_theta * res_old)) {
+        chord = false;
+        if (r == 0) P.hinv_ok[cell] = 0;
+        have_inv = false;
+      }
       if (P.one_shot) break;
     }
 
@@ -702,9 +856,12 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   }
 }
 
-template <int M, int NP>
-__global__ __launch_bounds__(256) void newton_kernel(DualParams P) {
-  newton_body<M, NP>(P, blockIdx.x);
+// The inexact-Hessian variant keeps the whole inverse row live through the
+// sweep; for NP <= 32 it is held to the exact kernel's two wavefronts per SIMD.
+template <int M, int NP, int PREC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
+void newton_kernel(DualParams P) {
+  newton_body<M, NP, PREC>(P, blockIdx.x);
 }
 
 // Problem k of a batched launch owns blocks begin[k] .. begin[k+1]-1.
@@ -718,6 +875,7 @@ __device__ __forceinline__ int batch_problem(const int* __restrict__ begin, int 
   return lo;
 }
 
+#ifdef IPM_HOST_UNIT  // defined once, in the host runtime's unit that launches it
 // Block offsets of a batched list-mode Newton launch, from the lists the
 // flux update filled: problem k gets ceil(listed_k / per_block) blocks from
 // begin[k] on, so all listed cells sit in the first blocks of the grid.  It
@@ -742,12 +900,13 @@ __global__ __launch_bounds__(64) void batch_prefix_kernel(const DualParams* __re
     if (lane == 0) begin[k + 1] = acc;
   }
 }
+#endif
 
-template <int M, int NP>
-__global__ __launch_bounds__(256) void newton_batched(const DualParams* __restrict__ PP,
-                                                      const int* __restrict__ begin, int n) {
+template <int M, int NP, int PREC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
+void newton_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
-  newton_body<M, NP>(PP[k], blockIdx.x - begin[k]);
+  newton_body<M, NP, PREC>(PP[k], blockIdx.x - begin[k]);
 }
 
 }  // namespace ipm

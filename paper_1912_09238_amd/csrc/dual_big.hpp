@@ -31,8 +31,9 @@
 //     as the partly inverted matrix is not symmetric), the inverse's tiles
 //     are kept in HBM, and later Newton iterations of the cell, in this and
 //     in following steps, take d = H_old^-1 g from them while each such
-//     iteration at least halves the dual residual; otherwise the next
-//     iteration assembles and inverts afresh.  The tau test stays exact, so
+//     iteration contracts the dual residual by a factor theta; otherwise the inverse is
+//     retired and the next iteration (one-shot: of the next pseudo-time
+//     step) assembles and inverts afresh.  The tau test stays exact, so
 //     the iteration stops at the same FP64 tolerance.
 #pragma once
 
@@ -196,6 +197,10 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   double* part = mvL + NPB;        // [16][NPB] row partial sums
   double* rowb = part;             // [2][NPB] pivot rows during the inversion
   bool chord = true;
+  // the cell's stored inverse is valid: read once, then kept in step with
+  // the flag this cell writes (no re-read of its own write)
+  bool have_inv = false;
+  if constexpr ((PREC & 2) != 0) have_inv = P.hinv_ok[cell] != 0;
   // d (unknown tid) = sum_c Hinv[tid][c] g[c] from the register tiles, the
   // column sums taken in a fixed order
   auto inverse_times = [&](const double (&A)[T][T], double gv) -> double {
@@ -233,7 +238,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     }
     // ---- inexact-Hessian Newton: the stored inverse while it contracts
     constexpr bool reuse = (PREC & 2) != 0;  // inexact-Hessian variant
-    const bool stale = reuse && chord && P.hinv_ok[cell];  // uniform
+    const bool stale = reuse && chord && have_inv;  // uniform
     double d = 0.0;
     double H[T][T];
     double* Hc = reuse ? P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) *
@@ -397,6 +402,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 #pragma unroll
         for (int j = 0; j < T; ++j) Hc[(i * T + j) * 256 + tid] = H[i][j];
       if (tid == 0) P.hinv_ok[cell] = 1;
+      have_inv = true;
       d = inverse_times(H, g);
     } else {
     // ---- Gauss-Jordan solve H d = g
@@ -492,8 +498,14 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     }
     const double res_old = res;
     res = gradient();
-    // a step from the stored inverse must at least halve the residual
-    if (stale && !(res <= 0.5 * res_old)) chord = false;
+    // a step from the stored inverse must contract the residual by theta, else
+    // the inverse is retired (the next iteration, in this or a later step,
+    // assembles afresh)
+    if (stale && !(res <= P.reuse_theta * res_old)) {
+      chord = false;
+      if (tid == 0) P.hinv_ok[cell] = 0;
+      have_inv = false;
+    }
     if (P.one_shot) break;
   }
 

@@ -18,11 +18,11 @@
 #include <vector>
 
 #include "ipm.h"
-#include "dual.hpp"
+// this unit defines the non-template kernels it launches itself
+#define IPM_HOST_UNIT
 #include "dual_big.hpp"
-#include "setup.hpp"
+#include "kernel_select.hpp"
 #include "tables.hpp"
-#include "update.hpp"
 
 using namespace ipm;
 
@@ -86,14 +86,16 @@ struct Problem {
   double* d_ctp = nullptr;  // analytic SG flux: triple products [N][N][N]
   // inexact-Hessian Newton (workgroup-kernel cells): stored inverse tiles
   int hessian_reuse = 0;
+  double reuse_theta = 0.5;
   unsigned char* d_hinv_ok = nullptr;  // [cells] stored inverse valid
   int* d_hinv_slot = nullptr;          // [cells] slot within the class's tiles
   // the class's tiles and size (set per launch)
   void set_hinv(DualParams& d, const DualClass& D) const {
     d.hinv = D.d_hinv;
     d.hinv_ok = d_hinv_ok;
-    d.hinv_stride = static_cast<long long>(D.T) * D.T * 256;
+    d.hinv_stride = static_cast<long long>(D.NP) * D.NP;
     d.hinv_slot = d_hinv_slot;
+    d.reuse_theta = reuse_theta;
   }
   StepCtrl* d_ctrl = nullptr;
   long long step_index = 0;
@@ -192,67 +194,9 @@ int pow2_at_least(int n, int lo) {
   return v;
 }
 
-using DualFn = void (*)(DualParams);
-using UpdFn = void (*)(UpdateParams);
-using SetupFn = void (*)(SetupParams);
-
-template <int M>
-DualFn dual_fn(int NP) {
-  switch (NP) {
-    case 8: return newton_kernel<M, 8>;
-    case 16: return newton_kernel<M, 16>;
-    case 32: return newton_kernel<M, 32>;
-    case 64: return newton_kernel<M, 64>;
-  }
-  return nullptr;
-}
-
-
-template <int M>
-DualFn big_fn(int T) {
-  switch (T) {
-    case 1: return newton_big_kernel<M, 1>;
-    case 2: return newton_big_kernel<M, 2>;
-    case 4: return newton_big_kernel<M, 4>;
-    case 5: return newton_big_kernel<M, 5>;
-    case 6: return newton_big_kernel<M, 6>;
-    case 8: return newton_big_kernel<M, 8>;
-    case 9: return newton_big_kernel<M, 9>;
-  }
-  return nullptr;
-}
-
-// prec bit 0: BF16-split MFMA Hessian; bit 1: inexact-Hessian Newton (both
-// for T >= 5 only)
-template <int M, int PR>
-DualFn big_fn_prec(int T) {
-  switch (T) {
-    case 5: return newton_big_kernel<M, 5, PR>;
-    case 6: return newton_big_kernel<M, 6, PR>;
-    case 8: return newton_big_kernel<M, 8, PR>;
-    case 9: return newton_big_kernel<M, 9, PR>;
-  }
-  return nullptr;
-}
-
-template <int M>
-DualFn big_fn_any(int T, int prec) {
-  switch (prec) {
-    case 1: return big_fn_prec<M, 1>(T);
-    case 2: return big_fn_prec<M, 2>(T);
-    case 3: return big_fn_prec<M, 3>(T);
-  }
-  return nullptr;
-}
-
 DualFn pick_big(int M, int T, int prec = 0) {
-  if (prec != 0) {
-    if (M == 1) return big_fn_any<1>(T, prec);
-    if (M == 4) return big_fn_any<4>(T, prec);
-    return nullptr;
-  }
-  if (M == 1) return big_fn<1>(T);
-  if (M == 4) return big_fn<4>(T);
+  if (M == 1) return big_pick<1>(T, prec);
+  if (M == 4) return big_pick<4>(T, prec);
   return nullptr;
 }
 
@@ -279,34 +223,24 @@ size_t big_lds_bytes(int M, int T, int Q, int kp, int prec = 0, bool bcache = tr
   return f(std::integral_constant<int, 4>{});
 }
 
-DualFn pick_dual(int M, int NP) {
-  if (M == 1) return dual_fn<1>(NP);
-  if (M == 3) return dual_fn<3>(NP);
-  if (M == 4) return dual_fn<4>(NP);
-  return nullptr;
-}
-
-template <int M>
-UpdFn upd_fn(int G) {
-  switch (G) {
-    case 16: return update_kernel<M, 16>;
-    case 32: return update_kernel<M, 32>;
-    case 64: return update_kernel<M, 64>;
-  }
+DualFn pick_dual(int M, int NP, int prec = 0) {
+  if (M == 1) return dual_pick<1>(NP, prec);
+  if (M == 3) return dual_pick<3>(NP, prec);
+  if (M == 4) return dual_pick<4>(NP, prec);
   return nullptr;
 }
 
 UpdFn pick_update(int M, int G) {
-  if (M == 1) return upd_fn<1>(G);
-  if (M == 3) return upd_fn<3>(G);
-  if (M == 4) return upd_fn<4>(G);
+  if (M == 1) return update_pick<1>(G);
+  if (M == 3) return update_pick<3>(G);
+  if (M == 4) return update_pick<4>(G);
   return nullptr;
 }
 
 SetupFn pick_setup(int M) {
-  if (M == 1) return setup_kernel<1>;
-  if (M == 3) return setup_kernel<3>;
-  return setup_kernel<4>;
+  if (M == 1) return setup_pick<1>();
+  if (M == 3) return setup_pick<3>();
+  return setup_pick<4>();
 }
 
 template <int M, int NP>
@@ -411,6 +345,9 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
       D.prec = (P.precision == IPM_PREC_BF16 ? 1 : 0) | (P.hessian_reuse ? 2 : 0);
     } else {
       D.NP = 8 << c;
+      // no BF16 Hessian below 65 unknowns; inexact-Hessian Newton on the
+      // register-row kernels only when asked for (hessian_reuse = 2)
+      D.prec = P.hessian_reuse == 2 ? 2 : 0;
       P.kp = std::max(P.kp, dual_table_columns(P.M, D.NP));
     }
   }
@@ -455,6 +392,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
       if (per_cu(D.waves) < 2 && 16 % P.M == 0) {
         D.T = std::max(1, D.NP / 16);
         D.NP = 16 * D.T;
+        D.prec = P.hessian_reuse ? 2 : 0;
       }
     }
     if (D.T > 0) {
@@ -477,7 +415,8 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   // largest small-cell class's launch (their unknowns fit its lane groups;
   // the kernel handles cells of any size up to its own)
   P.cls_map = 0x76543210u;
-  if (P.lists() && P.cells <= kMergeCells) {
+  // (not with inexact-Hessian Newton: the stored inverses are per class)
+  if (P.lists() && P.cells <= kMergeCells && P.hessian_reuse != 2) {
     int top = -1;
     for (int c = 0; c < 4; ++c)
       if (P.cls[c].configured && P.cls[c].count > 0 && P.cls[c].T == 0) top = c;
@@ -570,7 +509,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     hipLaunchKernelGGL(fn, dim3(items), dim3(256), D.lds, ctx->stream, d);
   } else {
-    DualFn fn = pick_dual(P.M, D.NP);
+    DualFn fn = pick_dual(P.M, D.NP, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP);
     const int blocks = (items + per_block - 1) / per_block;
@@ -690,65 +629,22 @@ ipm_status enqueue_close(ipm_ctx* ctx, Problem& P) {
 
 // ---------------------------------------------------------------- batching
 
-template <int M>
-const void* newton_batched_fn(int NP, int T, int prec) {
+const void* pick_newton_batched(int M, int NP, int T, int prec = 0) {
   if (T > 0) {
-    if constexpr (16 % M == 0) {
-      auto by_t = [&](auto pr) -> const void* {
-        constexpr int PR = decltype(pr)::value;
-        switch (T) {
-          case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5, PR>);
-          case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6, PR>);
-          case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8, PR>);
-          case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9, PR>);
-        }
-        return nullptr;
-      };
-      if (prec == 1) return by_t(std::integral_constant<int, 1>{});
-      if (prec == 2) return by_t(std::integral_constant<int, 2>{});
-      if (prec == 3) return by_t(std::integral_constant<int, 3>{});
-      switch (T) {
-        case 1: return reinterpret_cast<const void*>(newton_big_batched<M, 1>);
-        case 2: return reinterpret_cast<const void*>(newton_big_batched<M, 2>);
-        case 4: return reinterpret_cast<const void*>(newton_big_batched<M, 4>);
-        case 5: return reinterpret_cast<const void*>(newton_big_batched<M, 5>);
-        case 6: return reinterpret_cast<const void*>(newton_big_batched<M, 6>);
-        case 8: return reinterpret_cast<const void*>(newton_big_batched<M, 8>);
-        case 9: return reinterpret_cast<const void*>(newton_big_batched<M, 9>);
-      }
-    }
+    if (M == 1) return big_batched_pick<1>(T, prec);
+    if (M == 4) return big_batched_pick<4>(T, prec);
     return nullptr;
   }
-  switch (NP) {
-    case 8: return reinterpret_cast<const void*>(newton_batched<M, 8>);
-    case 16: return reinterpret_cast<const void*>(newton_batched<M, 16>);
-    case 32: return reinterpret_cast<const void*>(newton_batched<M, 32>);
-    case 64: return reinterpret_cast<const void*>(newton_batched<M, 64>);
-  }
-  return nullptr;
-}
-
-const void* pick_newton_batched(int M, int NP, int T, int prec = 0) {
-  if (M == 1) return newton_batched_fn<1>(NP, T, prec);
-  if (M == 3) return newton_batched_fn<3>(NP, T, prec);
-  if (M == 4) return newton_batched_fn<4>(NP, T, prec);
-  return nullptr;
-}
-
-template <int M>
-const void* update_batched_fn(int G) {
-  switch (G) {
-    case 16: return reinterpret_cast<const void*>(update_batched<M, 16>);
-    case 32: return reinterpret_cast<const void*>(update_batched<M, 32>);
-    case 64: return reinterpret_cast<const void*>(update_batched<M, 64>);
-  }
+  if (M == 1) return dual_batched_pick<1>(NP, prec);
+  if (M == 3) return dual_batched_pick<3>(NP, prec);
+  if (M == 4) return dual_batched_pick<4>(NP, prec);
   return nullptr;
 }
 
 const void* pick_update_batched(int M, int G) {
-  if (M == 1) return update_batched_fn<1>(G);
-  if (M == 3) return update_batched_fn<3>(G);
-  if (M == 4) return update_batched_fn<4>(G);
+  if (M == 1) return update_batched_pick<1>(G);
+  if (M == 3) return update_batched_pick<3>(G);
+  if (M == 4) return update_batched_pick<4>(G);
   return nullptr;
 }
 
@@ -1019,8 +915,12 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   // raise the dynamic LDS limit above the 64 KiB default (best effort)
   for (int M : {1, 3, 4})
     for (int NP : {8, 16, 32, 64})
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_dual(M, NP)),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      for (int prec : {0, 2}) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_dual(M, NP, prec)),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, big);
+        (void)hipFuncSetAttribute(pick_newton_batched(M, NP, 0, prec),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      }
   for (int M : {1, 3, 4})
     for (int G : {16, 32, 64})
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_update(M, G)),
@@ -1028,7 +928,7 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   for (int M : {1, 4})
     for (int T : {1, 2, 4, 5, 6, 8, 9})
       for (int prec : {0, 1, 2, 3}) {
-        if (prec != 0 && T < 5) continue;
+        if ((prec & 1) && T < 5) continue;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T, prec)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, big);
         (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T, prec),
@@ -1111,8 +1011,10 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
     if (pb->quad_rule != IPM_QUAD_GAUSS_LEGENDRE || pb->quad_per_dim < pb->degree + 1)
       return fail(ctx, IPM_E_ARG, "adaptivity needs the Gauss-Legendre rule with quad_per_dim >= degree + 1");
   }
-  if (pb->hessian_reuse != 0 && pb->hessian_reuse != 1)
-    return fail(ctx, IPM_E_ARG, "hessian_reuse must be 0 or 1");
+  if (pb->hessian_reuse < 0 || pb->hessian_reuse > 2)
+    return fail(ctx, IPM_E_ARG, "hessian_reuse must be 0, 1 or 2");
+  if (!(pb->reuse_theta >= 0.0 && pb->reuse_theta < 1.0))
+    return fail(ctx, IPM_E_ARG, "reuse_theta must be in [0, 1)");
   if (pb->hessian_reuse && pb->adapt)
     return fail(ctx, IPM_E_ARG, "hessian_reuse takes fixed degrees (adapt = 0)");
   if (pb->n_retard != 0) {
@@ -1193,16 +1095,17 @@ ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double* Phi, int
   return IPM_OK;
 }
 
-// inverse tiles of the inexact-Hessian Newton: cells with more than 64
-// unknowns, 16T x 16T doubles each (T of their size class), plus flags/slots
+// stored inverses of the inexact-Hessian Newton: NP x NP doubles per cell
+// (NP = 16T for the workgroup kernel; at least 16 for small cells, which
+// may run on it), plus flags/slots
 static size_t reuse_bytes(const ipm_problem* pb, int M, size_t cells) {
   size_t b = cells * (1 + sizeof(int));
   for (size_t c = 0; c < cells; ++c) {
     const int dg = pb->cell_degree ? pb->cell_degree[c] : pb->degree;
     const int n = M * binom_basis(pb->p, dg);
-    if (n <= 64) continue;
-    const int T = class_tiles(size_class(n));
-    b += sizeof(double) * 256 * static_cast<size_t>(T) * T;
+    const int k = size_class(n);
+    const size_t np = k >= 4 ? 16 * class_tiles(k) : std::max(16, 8 << k);
+    b += sizeof(double) * np * np;
   }
   return b;
 }
@@ -1297,6 +1200,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
   P.adapt = pb->adapt ? 1 : 0;
   P.hessian_reuse = pb->hessian_reuse;
+  P.reuse_theta = pb->reuse_theta > 0.0 ? pb->reuse_theta : 0.5;
   P.min_degree = pb->min_degree;
   P.delta_lo = pb->delta_lo;
   P.delta_hi = pb->delta_hi;
@@ -1388,7 +1292,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     bool any = false;
     for (DualClass& D : P.cls)
       if (D.configured && (D.prec & 2) && D.order_len > 0) {
-        ALLOC(D.d_hinv, static_cast<size_t>(D.order_len) * D.T * D.T * 256 * sizeof(double));
+        ALLOC(D.d_hinv, static_cast<size_t>(D.order_len) * D.NP * D.NP * sizeof(double));
         any = true;
       }
     if (any) {

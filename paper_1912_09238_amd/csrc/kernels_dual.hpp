@@ -1,0 +1,45 @@
+// Register-row Newton kernels (dual.hpp) of one variable count M; included
+// by one unit per M.
+#pragma once
+
+#include "kernel_select.hpp"
+
+namespace ipm {
+
+template <int M>
+DualFn dual_pick(int NP, int prec) {
+  if (prec == 2) switch (NP) {
+      case 8: return newton_kernel<M, 8, 2>;
+      case 16: return newton_kernel<M, 16, 2>;
+      case 32: return newton_kernel<M, 32, 2>;
+      case 64: return newton_kernel<M, 64, 2>;
+    }
+  if (prec != 0) return nullptr;
+  switch (NP) {
+    case 8: return newton_kernel<M, 8>;
+    case 16: return newton_kernel<M, 16>;
+    case 32: return newton_kernel<M, 32>;
+    case 64: return newton_kernel<M, 64>;
+  }
+  return nullptr;
+}
+
+template <int M>
+const void* dual_batched_pick(int NP, int prec) {
+  if (prec == 2) switch (NP) {
+      case 8: return reinterpret_cast<const void*>(newton_batched<M, 8, 2>);
+      case 16: return reinterpret_cast<const void*>(newton_batched<M, 16, 2>);
+      case 32: return reinterpret_cast<const void*>(newton_batched<M, 32, 2>);
+      case 64: return reinterpret_cast<const void*>(newton_batched<M, 64, 2>);
+    }
+  if (prec != 0) return nullptr;
+  switch (NP) {
+    case 8: return reinterpret_cast<const void*>(newton_batched<M, 8>);
+    case 16: return reinterpret_cast<const void*>(newton_batched<M, 16>);
+    case 32: return reinterpret_cast<const void*>(newton_batched<M, 32>);
+    case 64: return reinterpret_cast<const void*>(newton_batched<M, 64>);
+  }
+  return nullptr;
+}
+
+}  // namespace ipm

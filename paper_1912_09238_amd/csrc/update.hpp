@@ -420,6 +420,7 @@ __global__ __launch_bounds__(256) void update_batched(const UpdateParams* __rest
   update_body<M, G>(PP[k], blockIdx.x - begin[k]);
 }
 
+#ifdef IPM_HOST_UNIT  // defined once, in the host runtime's unit that launches it
 // One block: residual of the last update (fixed summation order) and, for
 // steady problems, the stop test eq:residualSteady <= eps.  Also folds the
 // per-block Newton counters into the control block when `close` is set.
@@ -469,5 +470,6 @@ __global__ __launch_bounds__(256) void residual_kernel(StepCtrl* C, const double
     }
   }
 }
+#endif
 
 }  // namespace ipm

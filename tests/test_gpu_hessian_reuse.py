@@ -62,8 +62,9 @@ def test_reuse_three_uncertainties_140_unknowns(gpu_ctx, orc):
 
 
 def test_reuse_uneven_degrees(gpu_ctx, orc):
-    """Per-cell degrees 1..4: only the 80- and 140-unknown classes keep
-    inverse tiles, each cell in its class's slot."""
+    """Per-cell degrees 1..4 (16, 40, 80 and 140 unknowns): every class
+    keeps its cells' inverses, each cell in its class's slot; the 16- and
+    40-unknown classes run on the workgroup kernel with 125 nodes."""
     spec = W.bump2d(n=10, degree=4, qpd=5, p=3, v1_spread=0.2)
     spec.update(ny=7, hessian_reuse=1)
     cd = np.random.default_rng(11).integers(1, 5, size=70).astype(np.int8)
@@ -82,6 +83,92 @@ def test_reuse_uneven_degrees(gpu_ctx, orc):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-8), err
+
+
+@pytest.mark.parametrize("case", ["sod_n30", "burgers_n5", "burgers_n10", "bump_n24", "bump_n40"])
+def test_reuse_small_kernels(gpu_ctx, orc, case):
+    """Register-row kernels: 32-lane groups with DPP broadcasts (Sod, 30
+    unknowns; 2D, 24), 16-lane groups (Burgers degree 9), LDS broadcasts
+    (Burgers degree 4, 8-lane groups; 2D degree 3, 40 unknowns in 64-lane
+    groups); hessian_reuse = 2 extends the inverse reuse to them."""
+    if case == "sod_n30":
+        spec, steps = W.sod(nx=250, degree=9, qpd=20), 40
+    elif case == "burgers_n5":
+        spec, steps = W.burgers_shock(nx=200, degree=4, qpd=10), 9
+    elif case == "burgers_n10":
+        spec, steps = W.burgers_shock(nx=150, degree=9, qpd=14), 8
+    elif case == "bump_n24":
+        spec, steps = W.bump2d(n=20, degree=2, qpd=6, p=2), 12
+        spec["ny"] = 14
+    else:
+        spec, steps = W.bump2d(n=16, degree=3, qpd=6, p=2), 10
+        spec["ny"] = 13
+    spec["hessian_reuse"] = 2
+    _run(gpu_ctx, orc, spec, steps)
+
+
+def test_reuse_small_kernel_sod_full_size(gpu_ctx, orc):
+    """The Sod workload at its full size (8192 cells, 30 unknowns)."""
+    spec = W.sod()
+    spec["hessian_reuse"] = 2
+    _run(gpu_ctx, orc, spec, 6)
+
+
+def test_reuse_one_shot_steady(gpu_ctx, orc):
+    """One-shot (one Newton step per pseudo-time step, from the stored
+    inverse while it halves the residual) reaches the same steady state as
+    the exact one-shot oracle."""
+    from paper_1912_09238_amd import binding
+    spec = W.steady_inflow(nx=100, degree=4, qpd=10, eps=1e-10, one_shot=1)
+    spec["hessian_reuse"] = 2
+    nodes, _ = binding.quadrature(1, 10)
+    _say("gpu case: hessian reuse, one-shot steady inflow to eps 1e-10")
+    pid = gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes),
+                              dirichlet=W.dirichlet_nodal(spec, nodes))
+    info = gpu_ctx.step(pid, 20000, wait=True)[0]
+    got = gpu_ctx.moments(pid)
+    gpu_ctx.release(pid)
+    ref = dict(spec)
+    ref.pop("hessian_reuse")
+    o = orc.Oracle(ref, ic_fn=lambda nd: W.ic_nodal(ref, nd),
+                   dirichlet_fn=lambda nd: W.dirichlet_nodal(ref, nd))
+    oinfo = o.step(20000)
+    _say("  steps gpu=%d oracle=%d" % (info["steps"], oinfo["steps"]))
+    assert info["status"] == 0 and info["done"] == 1
+    assert oinfo["status"] == 0 and oinfo["done"] == 1
+    err = parity(got, o.moments())
+    _say("  parity %s" % np.array2string(err, precision=2))
+    assert np.all(err <= 1e-7), err
+
+
+def test_reuse_small_batched_equals_alone(gpu_ctx):
+    """Small-kernel classes in a batch (Sod and Burgers, uneven degrees)
+    give the same bits as stepping alone."""
+    from paper_1912_09238_amd import binding
+    a = W.sod(nx=300, degree=9, qpd=20)
+    b = W.burgers_shock(nx=180, degree=6, qpd=10)
+    c = W.sod(nx=200, degree=9, qpd=20)
+    for x in (a, b, c):
+        x["hessian_reuse"] = 2
+    cds = [None, None, np.random.default_rng(2).integers(2, 10, size=200).astype(np.int8)]
+    _say("gpu case: hessian reuse, small kernels, three problems batched vs alone")
+
+    def make(spec, cd):
+        nodes, _ = binding.quadrature(1, spec["quad_per_dim"])
+        kw = {"cell_degree": cd} if cd is not None else {}
+        return gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes), **kw)
+    alone = []
+    for spec, cd in zip((a, b, c), cds):
+        pid = make(spec, cd)
+        gpu_ctx.step(pid, 9, wait=True)
+        alone.append(gpu_ctx.moments(pid))
+        gpu_ctx.release(pid)
+    ids = [make(spec, cd) for spec, cd in zip((a, b, c), cds)]
+    gpu_ctx.step(ids, 4, wait=True)
+    gpu_ctx.step(ids, 5, wait=True)
+    for k, pid in enumerate(ids):
+        assert np.array_equal(gpu_ctx.moments(pid), alone[k]), k
+        gpu_ctx.release(pid)
 
 
 def test_reuse_batched_equals_alone(gpu_ctx):
@@ -113,6 +200,26 @@ def test_reuse_needs_fixed_degrees(gpu_ctx):
     from paper_1912_09238_amd import binding
     spec = W.bump2d(n=8, degree=5, qpd=8, p=2)
     spec.update(hessian_reuse=1, adapt=1, min_degree=1, delta_lo=1e-6, delta_hi=1e-4)
+    nodes, _ = binding.quadrature(2, 8)
+    with pytest.raises(binding.IpmError) as e:
+        gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+    assert e.value.code == -1
+
+
+def test_reuse_stricter_contraction(gpu_ctx, orc):
+    """reuse_theta = 0.1: stale steps must cut the residual tenfold."""
+    spec = W.bump2d(n=16, degree=5, qpd=8, p=2)
+    spec.update(ny=12, hessian_reuse=1, reuse_theta=0.1)
+    _run(gpu_ctx, orc, spec, 10)
+
+
+@pytest.mark.parametrize("bad", [dict(hessian_reuse=3), dict(hessian_reuse=-1),
+                                 dict(hessian_reuse=1, reuse_theta=1.0),
+                                 dict(hessian_reuse=1, reuse_theta=-0.1)])
+def test_reuse_argument_errors(gpu_ctx, bad):
+    from paper_1912_09238_amd import binding
+    spec = W.bump2d(n=8, degree=5, qpd=8, p=2)
+    spec.update(bad)
     nodes, _ = binding.quadrature(2, 8)
     with pytest.raises(binding.IpmError) as e:
         gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
