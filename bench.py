@@ -79,7 +79,8 @@ def batch_form(args):
     per-cell total degree 1..4 (4..35 modes, 16..140 unknowns), 5^3 nodes,
     stepped together (one launch per kernel shape, graph replay); the same
     batch in the mixed-precision form (BF16 MFMA Hessians and inexact-Hessian
-    Newton on the workgroup-kernel cells) with its E/Var difference."""
+    Newton on every cell) and in the inexact-Hessian form alone, each with its
+    E/Var difference from the FP64 batch."""
     import torch
     from paper_1912_09238_amd import binding
     from paper_1912_09238_amd import workloads as W
@@ -127,28 +128,41 @@ def batch_form(args):
     seq_value = cells * seq_steps / (time.perf_counter() - t1)
     for pid in ids:
         ctx.release(pid)
-    # the mixed-precision batch: BF16 MFMA Hessians and the inexact-Hessian
-    # Newton (FP64 inverses reused) on the workgroup-kernel cells, FP64 tau
-    # test; the same warm-up and timed steps from the same initial states
-    pids = [ctx.set_problem(dict(spec, precision="bf16", hessian_reuse=1),
-                            ic_nodal=W.ic_nodal(spec, nodes), cell_degree=W.cell_degrees(spec))
-            for spec in specs]
-    ctx.step(pids, args.batch_warmup, wait=True)
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    ctx.step(pids, args.batch_steps)
-    torch.cuda.synchronize()
-    prec_elapsed = time.perf_counter() - t4
-    pafter = ctx.step(pids, 0, wait=True)
-    assert all(a["status"] == 0 for a in pafter), pafter
-    ev16 = e_var(pids)
-    for pid in pids:
-        ctx.release(pid)
-    num_e = sum(np.abs(a[0] - b[0]).sum() for a, b in zip(ev16, ev64))
-    den_e = sum(np.abs(b[0]).sum() for b in ev64)
-    num_v = sum(np.abs(a[1] - b[1]).sum() for a, b in zip(ev16, ev64))
-    den_v = sum(np.abs(b[1]).sum() for b in ev64)
-    prec_value = done / prec_elapsed
+    # the same problems, same warm-up and timed steps from the same initial
+    # states, in the mixed-precision form (BF16 MFMA Hessians, inexact-Hessian
+    # Newton with FP64 inverses reused on every cell, FP64 tau test) and in the
+    # inexact-Hessian form alone (FP64 Hessians)
+    forms = {}
+    for fname, extra, label in (
+            ("mixed_precision_batch", dict(precision="bf16", hessian_reuse=2),
+             "bf16 MFMA Hessian + inexact-Hessian Newton on all cells, FP64 tau"),
+            ("inexact_hessian_batch", dict(hessian_reuse=2),
+             "FP64 Hessian + inexact-Hessian Newton on all cells, FP64 tau")):
+        pids = [ctx.set_problem(dict(spec, **extra), ic_nodal=W.ic_nodal(spec, nodes),
+                                cell_degree=W.cell_degrees(spec)) for spec in specs]
+        ctx.step(pids, args.batch_warmup, wait=True)
+        pbefore = ctx.step(pids, 0, wait=True)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        ctx.step(pids, args.batch_steps)
+        torch.cuda.synchronize()
+        f_elapsed = time.perf_counter() - t4
+        pafter = ctx.step(pids, 0, wait=True)
+        assert all(a["status"] == 0 for a in pafter), pafter
+        ev = e_var(pids)
+        for pid in pids:
+            ctx.release(pid)
+        num_e = sum(np.abs(a[0] - b[0]).sum() for a, b in zip(ev, ev64))
+        den_e = sum(np.abs(b[0]).sum() for b in ev64)
+        num_v = sum(np.abs(a[1] - b[1]).sum() for a, b in zip(ev, ev64))
+        den_v = sum(np.abs(b[1]).sum() for b in ev64)
+        f_value = done / f_elapsed
+        forms[fname] = {"value": f_value, "speedup_vs_fp64": f_value / value,
+                        "ms_per_step": f_elapsed / args.batch_steps * 1e3, "form": label,
+                        "kbar": sum(a["newton_iters"] - b["newton_iters"]
+                                    for a, b in zip(pafter, pbefore)) / max(1, done),
+                        "rel_l1_vs_fp64": {"E": float(num_e / den_e), "Var": float(num_v / den_v)}}
+    prec_value = forms["mixed_precision_batch"]["value"]
     print("batch form: fp64 %.4g, bf16 + reuse %.4g cell-updates/s" % (value, prec_value),
           file=sys.stderr, flush=True)
     # many small problems: 64 Burgers shocks of 512 cells, degree 5 -- here the
@@ -181,11 +195,8 @@ def batch_form(args):
                    "cells_by_degree": {str(k): int(hist[k]) for k in range(1, 5)},
                    "parallelism": "single-gpu"},
         "one_problem_at_a_time": {"value": seq_value, "steps": seq_steps},
-        "mixed_precision_batch": {"value": prec_value, "speedup_vs_fp64": prec_value / value,
-                                  "ms_per_step": prec_elapsed / args.batch_steps * 1e3,
-                                  "form": "bf16 MFMA Hessian + inexact-Hessian Newton, FP64 tau",
-                                  "rel_l1_vs_fp64": {"E": float(num_e / den_e),
-                                                     "Var": float(num_v / den_v)}},
+        "mixed_precision_batch": forms["mixed_precision_batch"],
+        "inexact_hessian_batch": forms["inexact_hessian_batch"],
         "small_problems_64x512_burgers_deg5": {"batched": small_batched,
                                                 "one_problem_at_a_time": small_seq},
         "setup_s": t_setup, "autotuned_shapes": tuned,

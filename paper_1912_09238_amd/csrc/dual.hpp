@@ -27,8 +27,8 @@
 //      - inexact-Hessian variant (PREC bit 1; the outlook of Sec. 7 on not
 //        recomputing the Hessian): a fresh Hessian is inverted in place by
 //        the symmetric sweep (the matrix stays symmetric, so the broadcast
-//        pivot column again serves as the pivot row), the rows of -H^-1 go
-//        to HBM, and later iterations of the cell, in this and following
+//        pivot column again serves as the pivot row), the cell's n x n block
+//        of -H^-1 goes to HBM, and later iterations of the cell, in this and following
 //        steps, take d = H_old^-1 g from them while each such step
 //        contracts the dual residual by a factor theta; otherwise the inverse is retired and the
 //        next iteration (one-shot: of the next pseudo-time step) assembles
@@ -471,10 +471,13 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
       if constexpr (reuse) {
         if (chord && have_inv) {  // uniform in the group
           fresh = false;
+          // only the cell's n x n block is stored; the mat-vec below reads
+          // live rows only, and their entries beyond column n are zero
 #pragma unroll
           for (int s = 0; s < R; ++s)
 #pragma unroll
-            for (int c = 0; c < NP; ++c) row[s][c] = Hc[c * NP + ro[s]];
+            for (int c = 0; c < NP; ++c)
+              row[s][c] = (live[s] && c < nc) ? Hc[c * NP + ro[s]] : 0.0;
         }
       }
       if (fresh) {
@@ -604,7 +607,8 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 #pragma unroll
           for (int s = 0; s < R; ++s)
 #pragma unroll
-            for (int c = 0; c < NP; ++c) Hc[c * NP + ro[s]] = row[s][c];
+            for (int c = 0; c < NP; ++c)
+              if (live[s] && c < nc) Hc[c * NP + ro[s]] = row[s][c];
           if (r == 0) P.hinv_ok[cell] = 1;
           have_inv = true;
         } else {

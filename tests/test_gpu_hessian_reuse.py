@@ -61,22 +61,26 @@ def test_reuse_three_uncertainties_140_unknowns(gpu_ctx, orc):
     _run(gpu_ctx, orc, spec, 6)
 
 
-def test_reuse_uneven_degrees(gpu_ctx, orc):
-    """Per-cell degrees 1..4 (16, 40, 80 and 140 unknowns): every class
-    keeps its cells' inverses, each cell in its class's slot; the 16- and
-    40-unknown classes run on the workgroup kernel with 125 nodes."""
+@pytest.mark.parametrize("level,precision", [(1, "fp64"), (2, "fp64"), (2, "bf16")])
+def test_reuse_uneven_degrees(gpu_ctx, orc, level, precision):
+    """Per-cell degrees 1..4 (16, 40, 80 and 140 unknowns), 125 nodes: the
+    16-unknown class runs on the workgroup kernel, the 40-unknown class on
+    the 64-lane register-row kernel (inverse reuse only at level 2); each
+    cell keeps its inverse in its class's slot."""
     spec = W.bump2d(n=10, degree=4, qpd=5, p=3, v1_spread=0.2)
-    spec.update(ny=7, hessian_reuse=1)
+    spec.update(ny=7, hessian_reuse=level, precision=precision)
     cd = np.random.default_rng(11).integers(1, 5, size=70).astype(np.int8)
     from paper_1912_09238_amd import binding
     nodes, _ = binding.quadrature(3, 5)
-    _say("gpu case: hessian reuse, uneven degrees 1..4, p=3, 70 cells, 6 steps")
+    _say("gpu case: hessian reuse %d (%s), uneven degrees 1..4, p=3, 70 cells, 6 steps" % (
+        level, precision))
     pid = gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes), cell_degree=cd)
     info = gpu_ctx.step(pid, 6, wait=True)[0]
     got = gpu_ctx.moments(pid)
     gpu_ctx.release(pid)
     ref = dict(spec)
     ref.pop("hessian_reuse")
+    ref.pop("precision")
     o = orc.Oracle(ref, ic_fn=lambda nd: W.ic_nodal(ref, nd), cell_degree=cd)
     oinfo = o.step(6)
     assert info["status"] == 0 and oinfo["status"] == 0
