@@ -283,6 +283,22 @@ def serve_form(args):
     lat = np.array([r["latency"] for r in res])
     work = sum(r["steps"] * rq["spec"]["nx"] for r, rq in zip(res, reqs))
     makespan = max(r["finished"] for r in res)
+    # the same 1D stream in the reduced-precision request form: BF16 Hessian
+    # (which the register-row kernels of these cells, n <= 30, do not use)
+    # and the inexact-Hessian Newton on every cell
+    rq_m = [dict(rq, spec=dict(rq["spec"], precision="bf16", hessian_reuse=2)) for rq in reqs]
+    res_m = ctx.serve(rq_m, steps_per_round=args.round, max_active=args.max_active, moments=False)
+    assert all(r["status"] == 0 for r in res_m), [r for r in res_m if r["status"]][:3]
+    lat_m = np.array([r["latency"] for r in res_m])
+    work_m = sum(r["steps"] * rq["spec"]["nx"] for r, rq in zip(res_m, reqs))
+    span_m = max(r["finished"] for r in res_m)
+    one_d_mixed = {"form": "bf16 + inexact-Hessian Newton on every cell (BF16 unused at n <= 30)",
+                   "served_cell_updates_per_s": work_m / span_m, "makespan_s": span_m,
+                   "latency_s": {"p50": float(np.percentile(lat_m, 50)),
+                                 "p99": float(np.percentile(lat_m, 99))},
+                   "served_ratio_vs_fp64": (work_m / span_m) / (work / makespan)}
+    print("serve form, 1D mixed: %.4g cell-updates/s, p50 %.3f s" % (
+        work_m / span_m, one_d_mixed["latency_s"]["p50"]), file=sys.stderr, flush=True)
     # 2D requests (21 unknowns per variable, 84 per cell), where the precision
     # form applies: the same stream served in the FP64 form and in the
     # mixed-precision form (BF16 Hessian + inverse reuse), at an open-loop
@@ -338,6 +354,7 @@ def serve_form(args):
                       "max": float(lat.max())},
         "offered_cell_updates_per_s": work / args.duration,
         "served_cell_updates_per_s": work / makespan, "makespan_s": makespan, "wall_s": wall,
+        "requests_1d_mixed": one_d_mixed,
         "requests_2d_fp64_vs_mixed": two_d,
     }
 
