@@ -17,9 +17,10 @@
  * Parity pins: every function here is pinned by the "not gpu" tests against
  * closed forms, special cases (stochastic Galerkin, deterministic finite
  * volumes, coupled collocation at N = Q), invariants (conservation, maximum
- * principle, dual round trip) and brute-force collocation.  The exact
- * moment trajectories for N < Q with a non-quadratic entropy are fixed by
- * nothing but this oracle ("parity unpinned" for that case).
+ * principle, dual round trip, decay of the total entropy) and brute-force
+ * collocation.  The exact moment trajectories for N < Q with a
+ * non-quadratic entropy are pinned by the entropy decay only, not to exact
+ * values ("parity unpinned" for their exact values).
  */
 #ifndef IPM_ORACLE_H
 #define IPM_ORACLE_H
