@@ -64,3 +64,25 @@ def test_total_entropy_decays_sod_euler(orc):
     inc = np.diff(hist)
     assert np.all(inc <= 1e-9 * abs(hist[0])), inc.max()
     assert hist[-1] < hist[0]
+
+
+def test_total_entropy_decays_euler_2d(orc):
+    """Two uncertainties on the periodic square (tensor weights are products
+    of the 1D weights, whatever the node order)."""
+    spec = W.bump2d(n=16, degree=3, qpd=5, p=2)
+    w1 = _weights(5)
+    w2 = np.outer(w1, w1).ravel()
+
+    def s2(U):
+        rho, mx, my, E = U[..., 0], U[..., 1], U[..., 2], U[..., 3]
+        p = (GAMMA - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho)
+        return -rho * np.log(p * rho ** (-GAMMA)) / (GAMMA - 1.0)
+
+    o = orc.Oracle(spec, ic_fn=lambda nd: W.ic_nodal(spec, nd))
+    hist = [float(np.sum(s2(o.nodal()) * w2[None, :]))]
+    for _ in range(20):
+        assert o.step(1)["status"] == 0
+        hist.append(float(np.sum(s2(o.nodal()) * w2[None, :])))
+    inc = np.diff(hist)
+    assert np.all(inc <= 1e-9 * abs(hist[0])), inc.max()
+    assert hist[-1] < hist[0]
