@@ -482,39 +482,39 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
       }
       if (fresh) {
         // ---- Hessian rows in registers; identity beyond the nc unknowns
-  #pragma unroll
+#pragma unroll
         for (int s = 0; s < R; ++s)
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < NP; ++c) row[s][c] = 0.0;
         {
           int aidx[R][M];
           double live_f[R];
-  #pragma unroll
+#pragma unroll
           for (int s = 0; s < R; ++s) {
             live_f[s] = live[s] ? 1.0 : 0.0;
-  #pragma unroll
+#pragma unroll
             for (int b = 0; b < M; ++b) aidx[s][b] = Packed<M>::idx(aa[s], b);
           }
           for (int q = 0; q < Q; ++q) {
             const double* Jq = JS + q * NJ;
             double sb[R][M];
-  #pragma unroll
+#pragma unroll
             for (int s = 0; s < R; ++s) {
               const double wi = wphiL[q * kp + ii[s]] * live_f[s];
-  #pragma unroll
+#pragma unroll
               for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
             }
             const_dptr ph = phiC + q * kp;  // uniform: scalar loads
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < NP; ++c) {
               const double v = ph[c / M];
-  #pragma unroll
+#pragma unroll
               for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
             }
           }
-  #pragma unroll
+#pragma unroll
           for (int s = 0; s < R; ++s)
-  #pragma unroll
+#pragma unroll
             for (int c = 0; c < NP; ++c)
               row[s][c] = (live[s] && c < nc) ? row[s][c] : (c == ro[s] ? 1.0 : 0.0);
         }
@@ -664,21 +664,21 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
             // LDS broadcast: the step reads the whole column in one batch,
             // updates and publishes the next column first, then the rest of the
             // row while that write lands
-    #pragma unroll
+#pragma unroll
             for (int s = 0; s < R; ++s) {
               x[s] = g[s];
               cA[ro[s]] = row[s][0];
             }
             if (r == 0) cX[0] = x[0];
             wave_sync();
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NP; ++k) {
               // steps beyond the cell's unknowns would only touch the identity block
               if (k < nc) {
                 const double* A = cA + (k & 1) * NP;
                 double* An = cA + ((k + 1) & 1) * NP;
                 double col[NP];
-    #pragma unroll
+#pragma unroll
                 for (int j = k; j < NP; ++j) col[j] = A[j];
                 const double gk = cX[k & 1];
                 const double piv = col[k];
@@ -686,22 +686,22 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
                 if (r == k % G) cP[k] = piv;
                 const double rp = recip(piv);
                 double f[R];
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < R; ++s) {
                   f[s] = (ro[s] == k) ? 0.0 : row[s][k] * rp;
                   x[s] = fma(-f[s], gk, x[s]);
                 }
                 if (k + 1 < NP) {
-    #pragma unroll
+#pragma unroll
                   for (int s = 0; s < R; ++s) {
                     row[s][k + 1] = fma(-f[s], col[k + 1], row[s][k + 1]);
                     An[ro[s]] = row[s][k + 1];
                   }
                   if (r == (k + 1) % G) cX[(k + 1) & 1] = x[(k + 1) / G];
                 }
-    #pragma unroll
+#pragma unroll
                 for (int j = k + 2; j < NP; ++j)
-    #pragma unroll
+#pragma unroll
                   for (int s = 0; s < R; ++s) row[s][j] = fma(-f[s], col[j], row[s][j]);
                 wave_sync();
               }
@@ -711,7 +711,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
               break;
             }
             wave_sync();
-    #pragma unroll
+#pragma unroll
             for (int s = 0; s < R; ++s) d[s] = live[s] ? x[s] * recip(cP[ro[s]]) : 0.0;
           }
 
