@@ -550,17 +550,18 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 }
 
 // PREC bit 0: BF16-split MFMA Hessian; bit 1: inexact-Hessian Newton.
-// Two workgroups per CU for the precision form up to T = 6 (its per-cell
-// latency is the lower one, so the launch is occupancy bound); larger tiles
-// do not fit two wavefronts' registers
+// Two workgroups per CU for the BF16 variants up to T = 6, with or without
+// inverse reuse (their per-cell latency is the lower one, so the launch is
+// occupancy bound; uncapped, the MFMA accumulators push the register count
+// just past two wavefronts' share); larger tiles do not fit
 template <int M, int T, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 1 && T <= 6) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
 void newton_big_kernel(DualParams P) {
   newton_big_body<M, T, PREC>(P, blockIdx.x);
 }
 
 template <int M, int T, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 1 && T <= 6) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
 void newton_big_batched(const DualParams* __restrict__ PP,
                                                           const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
