@@ -111,15 +111,22 @@ __device__ __forceinline__ const double* neighbour_nodal(const UpdateParams& P, 
 }
 
 // largest wave speeds of the step: the first wavefront reads the 64 slots,
-// one per lane, and reduces them; the result is shared through LDS.
-__device__ __forceinline__ void step_speeds(const StepCtrl* C, int parity, int dim, double& ax,
-                                            double& ay, double* sh) {
+// one per lane (step_slots, issued early), and reduces them; the result is
+// shared through LDS.
+__device__ __forceinline__ void step_slots(const StepCtrl* C, int parity, int dim, double& vx,
+                                           double& vy) {
+  vx = vy = 0.0;
   if (threadIdx.x < 64) {
     const int s = threadIdx.x;
-    double vx = __longlong_as_double(static_cast<long long>(C->amax[parity][0][s * kSlotStride]));
-    double vy = dim == 2 ? __longlong_as_double(
-                               static_cast<long long>(C->amax[parity][1][s * kSlotStride]))
-                         : 0.0;
+    vx = __longlong_as_double(static_cast<long long>(C->amax[parity][0][s * kSlotStride]));
+    if (dim == 2)
+      vy = __longlong_as_double(static_cast<long long>(C->amax[parity][1][s * kSlotStride]));
+  }
+}
+
+__device__ __forceinline__ void step_speeds(const StepCtrl* C, double vx, double vy, double& ax,
+                                            double& ay, double* sh) {
+  if (threadIdx.x < 64) {
     vx = wave_max(vx);
     vy = wave_max(vy);
     if (threadIdx.x == 0) {
@@ -135,13 +142,13 @@ __device__ __forceinline__ void step_speeds(const StepCtrl* C, int parity, int d
 template <int M, int G>
 __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk) {
   StepCtrl* C = P.ctrl;
-  if (C->done[P.parity] || C->status) {
-    if (blk == 0 && threadIdx.x == 0) {
-      C->done[P.parity ^ 1] = 1;
-      C->t[P.parity ^ 1] = C->t[P.parity];
-    }
-    return;
-  }
+  // independent loads first, so that their round trips overlap: the stop
+  // flags, the step's speed slots, and (below) the tables, this lane's first
+  // nodes of the cell and its neighbours and its first old moment
+  const int stop_done = C->done[P.parity];
+  const unsigned stop_status = C->status;
+  double slot_x, slot_y;
+  step_slots(C, P.parity, P.dim, slot_x, slot_y);
   extern __shared__ double smem[];
   const int Q = P.Q, kp = P.kp, N = P.N;
   double* wphiL = smem;
@@ -186,8 +193,15 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
     }
     if (r < M * N) uold0 = P.uold[static_cast<size_t>(cell) * M * N + r];
   }
+  if (stop_done || stop_status) {  // uniform: the block leaves before any barrier
+    if (blk == 0 && threadIdx.x == 0) {
+      C->done[P.parity ^ 1] = 1;
+      C->t[P.parity ^ 1] = C->t[P.parity];
+    }
+    return;
+  }
   double ax, ay;
-  step_speeds(C, P.parity, P.dim, ax, ay, sh_speed);
+  step_speeds(C, slot_x, slot_y, ax, ay, sh_speed);
   const double t0 = C->t[P.parity];
   double dt = P.dim == 2 ? P.cfl / (ax / P.dx + ay / P.dy) : P.cfl * P.dx / ax;
   bool last = false;
