@@ -346,15 +346,18 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   using Cfg = NewtonCfg<M, NP>;
   constexpr int G = Cfg::G, CPW = Cfg::CPW, NJ = Cfg::NJ, R = Cfg::R;
   constexpr bool kDpp = Cfg::kDpp;
-  if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
-  // the flux update of this step fills the next step's speed slots and lists
-  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  // the stop flags are read with the list lengths (one round trip, not two);
+  // a stopped problem's block leaves right after, before any write
+  const bool stop = P.mode == 0 && ((P.ctrl->done[P.parity] != 0) | (P.ctrl->status != 0u));
   const int waves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int grp = lane / G;
   const int r = lane % G;
   const int cell = work_cell(P, (blk * waves + wave) * CPW + grp);
+  if (stop) return;  // uniform
+  // the flux update of this step fills the next step's speed slots and lists
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   if (!__syncthreads_or(cell >= 0)) return;
 
   const int Q = P.Q, kp = P.kp, N = P.N;

@@ -95,9 +95,11 @@ template <int M, int T, int PREC>
 __device__ __forceinline__ void newton_big_body(const DualParams& P, const int blk) {
   using Cfg = BigCfg<M, T, PREC>;
   constexpr int NPB = Cfg::NPB, NJ = Cfg::NJ;
-  if (P.mode == 0 && (P.ctrl->done[P.parity] || P.ctrl->status)) return;
-  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  // the stop flags are read with the list lengths (one round trip, not two)
+  const bool stop = P.mode == 0 && ((P.ctrl->done[P.parity] != 0) | (P.ctrl->status != 0u));
   const int cell = work_cell(P, blk);
+  if (stop) return;  // uniform
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   if (cell < 0) return;  // uniform over the workgroup
 
   const int Q = P.Q, kp = P.kp, N = P.N;
