@@ -361,6 +361,25 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   if (!__syncthreads_or(cell >= 0)) return;
 
   const int Q = P.Q, kp = P.kp, N = P.N;
+  // the cell's dual and moments are requested before the tables are staged,
+  // so the two memory round trips overlap; unknown (i, a) of row
+  // ro = i * M + a; rows r + s * G of this lane
+  const int Nc = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) : 0;
+  const int nc = Nc * M;
+  int ro[R], ii[R], aa[R];
+  bool live[R];
+  size_t gidx[R];
+  double lam[R], uh[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    ro[s] = r + s * G;
+    ii[s] = ro[s] / M;
+    aa[s] = ro[s] % M;
+    live[s] = ro[s] < nc;
+    gidx[s] = static_cast<size_t>(cell >= 0 ? cell : 0) * M * N + static_cast<size_t>(aa[s]) * N + ii[s];
+    lam[s] = live[s] ? P.lam[gidx[s]] : 0.0;
+    uh[s] = live[s] ? P.uhat[gidx[s]] : 0.0;
+  }
   extern __shared__ double smem[];
   double* phiL = smem;
   double* wphiL = phiL + Q * kp;
@@ -382,33 +401,16 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   // elimination steps the wavefront runs: the largest unknown count of its
   // cells (wave-uniform, so each step is a scalar branch; smaller cells see
   // only identity rows in the extra steps)
-  const int nc_lane = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) * M : 0;
   const int kmax =
-      __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max(static_cast<double>(nc_lane))));
+      __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max(static_cast<double>(nc))));
   (void)kmax;
 
   int its = 0;
   unsigned status = 0;
   double sx = 0.0, sy = 0.0;
   if (cell >= 0) {
-    const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
-    const int nc = Nc * M;
-    // unknown (i, a) of row ro = i * M + a; rows r + s * G of this lane
-    int ro[R], ii[R], aa[R];
-    bool live[R];
-    size_t gidx[R];
-    double lam[R], uh[R];
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      ro[s] = r + s * G;
-      ii[s] = ro[s] / M;
-      aa[s] = ro[s] % M;
-      live[s] = ro[s] < nc;
-      gidx[s] = static_cast<size_t>(cell) * M * N + static_cast<size_t>(aa[s]) * N + ii[s];
-      lam[s] = live[s] ? P.lam[gidx[s]] : 0.0;
-      uh[s] = live[s] ? P.uhat[gidx[s]] : 0.0;
-      lamS[ro[s]] = lam[s];
-    }
+    for (int s = 0; s < R; ++s) lamS[ro[s]] = lam[s];
     wave_sync();
     double ssum = 0.0;
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
