@@ -46,7 +46,7 @@ struct DualClass {
   int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
   int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
   bool merged = false;      // its cells go to the lists of a larger class
-  double* d_hinv = nullptr; // inexact-Hessian Newton: inverse tiles of the class's cells
+  double* d_hinv = nullptr; // inexact-Hessian Newton: stored inverses of the class's cells
 };
 
 // Problems up to this many cells are latency bound: one Newton launch for
@@ -84,11 +84,11 @@ struct Problem {
   // adaptive: the update of a step writes the other parity's buffer)
   int8_t* d_cellN[2] = {nullptr, nullptr};
   double* d_ctp = nullptr;  // analytic SG flux: triple products [N][N][N]
-  // inexact-Hessian Newton (workgroup-kernel cells): stored inverse tiles
+  // inexact-Hessian Newton: 1 = cells on the workgroup kernel, 2 = every cell
   int hessian_reuse = 0;
   double reuse_theta = 0.5;
   unsigned char* d_hinv_ok = nullptr;  // [cells] stored inverse valid
-  int* d_hinv_slot = nullptr;          // [cells] slot within the class's tiles
+  int* d_hinv_slot = nullptr;          // [cells] slot within the class's inverses
   // the class's tiles and size (set per launch)
   void set_hinv(DualParams& d, const DualClass& D) const {
     d.hinv = D.d_hinv;
@@ -1288,7 +1288,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   if (P.flux == IPM_FLUX_SG_ANALYTIC)
     ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
   if (P.hessian_reuse) {
-    // tiles for the cells of each inexact-Hessian class only
+    // NP x NP doubles for the cells of each inexact-Hessian class only
     bool any = false;
     for (DualClass& D : P.cls)
       if (D.configured && (D.prec & 2) && D.order_len > 0) {
