@@ -108,3 +108,20 @@ def test_served_mixed_precision_2d_equals_alone(gpu_ctx):
         info, mom = _alone(gpu_ctx, rq)
         assert r["steps"] == info["steps"]
         assert np.array_equal(r["moments"], mom), k
+
+
+def test_served_inexact_hessian_1d_equals_alone(gpu_ctx):
+    """1D requests in the reduced-precision request form (inverse reuse on
+    every cell; the stored inverses stay with each resident problem): served
+    in a mix, each equals the same problem stepped alone."""
+    reqs = []
+    for rq in _requests():
+        rq = dict(rq, spec=dict(rq["spec"], precision="bf16", hessian_reuse=2))
+        reqs.append(rq)
+    _say("gpu case: serve %d 1D requests with hessian_reuse=2, rounds of 4 steps" % len(reqs))
+    res = gpu_ctx.serve(reqs, steps_per_round=4, max_active=4)
+    for k, (rq, r) in enumerate(zip(reqs, res)):
+        assert r["status"] == 0, (k, r)
+        info, mom = _alone(gpu_ctx, rq)
+        assert r["steps"] == info["steps"]
+        assert np.array_equal(r["moments"], mom), k
