@@ -229,6 +229,15 @@ __device__ __forceinline__ double recip(double x) {
   return r;
 }
 
+// 1/x with one Newton step (relative error about 2e-15): the elimination
+// multipliers of the register-row solve, where the reciprocal sits on every
+// pivot step's dependency chain; the dual update itself stays exact to
+// rounding through the final division by the pivots (recip)
+__device__ __forceinline__ double recip1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+
 // Ansatz at the nodes q = q0, q0 + step, ... of one cell for the dual lamS
 // (interleaved, first Nc modes).  Writes u and packed J to LDS, adds the
 // lane's share of <s_*> to ssum.  Returns the admissible flag.
@@ -645,7 +654,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
                 const double gk = (k < 16) ? row_bcast<k % 16>(xlo) : row_bcast<k % 16>(xhi);
                 pd_ok &= piv > 0.0 ? 1 : 0;
                 if (r == k) dg = piv;
-                const double f = (r == k) ? 0.0 : row[0][k] * recip(piv);
+                const double f = (r == k) ? 0.0 : row[0][k] * recip1(piv);
                 const double negf = -f;
                 xv = fma(-f, gk, xv);
                 dpp_guard(clo, chi);
