@@ -380,7 +380,10 @@ def adapt_form(args):
     ic = W.ic_nodal(base, nodes)
     cells = base["nx"] * base["ny"]
     res = {}
-    for name, sp in (("fixed", base), ("adaptive", spec)):
+    # the adaptive run also with inverse reuse (BF16 Hessian): the
+    # precision form on top of the adaptivity
+    spec_r = dict(spec, hessian_reuse=1, precision="bf16")
+    for name, sp in (("fixed", base), ("adaptive", spec), ("adaptive_reuse", spec_r)):
         pid = ctx.set_problem(sp, ic_nodal=ic)
         ctx.step(pid, args.prec_warmup, wait=True)
         b = ctx.step(pid, 0, wait=True)[0]
@@ -394,7 +397,8 @@ def adapt_form(args):
         dg = ctx.degrees(pid)
         res[name] = {"value": cells * args.prec_steps / el, "ms_per_step": el / args.prec_steps * 1e3,
                      "kbar": (a["newton_iters"] - b["newton_iters"]) / (cells * args.prec_steps),
-                     "moments": ctx.moments(pid), "levels": np.bincount(dg, minlength=6)}
+                     "moments": ctx.moments(pid), "levels": np.bincount(dg, minlength=6),
+                     "degrees": dg}
         ctx.release(pid)
         print("adaptive form, 2D: %s %.4g cell-updates/s" % (name, res[name]["value"]),
               file=sys.stderr, flush=True)
@@ -439,6 +443,17 @@ def adapt_form(args):
         "fixed_degree5": {"value": res["fixed"]["value"], "ms_per_step": res["fixed"]["ms_per_step"],
                           "kbar": res["fixed"]["kbar"]},
         "speedup_vs_fixed": res["adaptive"]["value"] / res["fixed"]["value"],
+        "adaptive_with_bf16_inverse_reuse": {
+            "value": res["adaptive_reuse"]["value"],
+            "ms_per_step": res["adaptive_reuse"]["ms_per_step"],
+            "kbar": res["adaptive_reuse"]["kbar"],
+            "speedup_vs_fixed": res["adaptive_reuse"]["value"] / res["fixed"]["value"],
+            "rel_l1_vs_adaptive": {
+                "E": rel(res["adaptive_reuse"]["moments"][:, :, 0], ma[:, :, 0]),
+                "Var": rel(np.sum(res["adaptive_reuse"]["moments"][:, :, 1:] ** 2, axis=2),
+                           np.sum(ma[:, :, 1:] ** 2, axis=2))},
+            "cells_with_other_level": int(np.sum(res["adaptive_reuse"]["degrees"] !=
+                                                  res["adaptive"]["degrees"]))},
         "kbar": res["adaptive"]["kbar"],
         "final_levels": {str(k): int(v) for k, v in enumerate(lv) if v},
         "mean_unknowns_per_cell": float((lv * n_of).sum() / lv.sum()),

@@ -148,15 +148,18 @@ typedef struct {
   /* Inexact-Hessian Newton (the outlook of Sec. 7: do not recompute the
      Hessian at every iteration) for the cells on the workgroup kernel (more
      than 64 unknowns, or many quadrature nodes): 1 = each such cell keeps
-     the inverse of its last freshly assembled Hessian in device memory (FP64, NP x NP doubles with
-     NP = n rounded up to 8, 16, 32 or 64 for n <= 64 and to a multiple of 16
-     above: 8 KB per cell at n = 30, about 74 KB at n = 84) and takes later
+     the inverse of its last freshly assembled Hessian in device memory
+     (FP64, NP x NP doubles with NP = n rounded up to 8, 16, 32 or 64 for
+     n <= 64 and to a multiple of 16 above: 8 KB per cell at n = 30, about
+     74 KB at n = 84) and takes later
      Newton steps, in this and following time steps, as d = H_old^-1 grad L
      while each such step contracts the dual residual by reuse_theta;
      otherwise the inverse is retired and the next iteration (one-shot: of
      the next pseudo-time step) assembles and inverts afresh.  The tau test is
      unchanged, so the dual still converges to tau; results agree with exact
-     Newton within the dual tolerance, not bit for bit.  Fixed degrees only.
+     Newton within the dual tolerance, not bit for bit.  With adaptive
+     levels each cell keeps one slot of the largest class's size and a level
+     change retires the cell's inverse.
      2 = the same for every cell, also on the register-row kernels (n <= 64;
      slower than exact Newton on the 1D workloads measured, where those
      solves are cheap and the launches latency bound; with it the Newton

@@ -89,12 +89,16 @@ struct Problem {
   double reuse_theta = 0.5;
   unsigned char* d_hinv_ok = nullptr;  // [cells] stored inverse valid
   int* d_hinv_slot = nullptr;          // [cells] slot within the class's inverses
-  // the class's tiles and size (set per launch)
+  // with adaptive levels: one slot per cell of the largest class's size (a
+  // cell moves between classes; a level change retires its inverse)
+  double* d_hinv_all = nullptr;
+  long long hinv_all_stride = 0;
+  // the class's inverses and their size (set per launch)
   void set_hinv(DualParams& d, const DualClass& D) const {
-    d.hinv = D.d_hinv;
+    d.hinv = hinv_all_stride ? d_hinv_all : D.d_hinv;
     d.hinv_ok = d_hinv_ok;
-    d.hinv_stride = static_cast<long long>(D.NP) * D.NP;
-    d.hinv_slot = d_hinv_slot;
+    d.hinv_stride = hinv_all_stride ? hinv_all_stride : static_cast<long long>(D.NP) * D.NP;
+    d.hinv_slot = hinv_all_stride ? nullptr : d_hinv_slot;
     d.reuse_theta = reuse_theta;
   }
   StepCtrl* d_ctrl = nullptr;
@@ -302,7 +306,7 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv_ok, P->d_hinv_slot};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv_ok, P->d_hinv_slot, P->d_hinv_all};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
@@ -577,6 +581,7 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.retard = P.d_retard;
   u.cls_map = P.cls_map;
   u.ctp = P.d_ctp;
+  u.hinv_ok = P.adapt ? P.d_hinv_ok : nullptr;
   return u;
 }
 
@@ -1015,8 +1020,6 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
     return fail(ctx, IPM_E_ARG, "hessian_reuse must be 0, 1 or 2");
   if (!(pb->reuse_theta >= 0.0 && pb->reuse_theta < 1.0))
     return fail(ctx, IPM_E_ARG, "reuse_theta must be in [0, 1)");
-  if (pb->hessian_reuse && pb->adapt)
-    return fail(ctx, IPM_E_ARG, "hessian_reuse takes fixed degrees (adapt = 0)");
   if (pb->n_retard != 0) {
     if (!pb->adapt || !(pb->steady_eps > 0.0))
       return fail(ctx, IPM_E_ARG, "refinement retardation needs adapt = 1 and steady_eps > 0");
@@ -1100,6 +1103,11 @@ ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double* Phi, int
 // may run on it), plus flags/slots
 static size_t reuse_bytes(const ipm_problem* pb, int M, size_t cells) {
   size_t b = cells * (1 + sizeof(int));
+  if (pb->adapt) {  // one slot per cell of the largest class's size
+    const int k = size_class(M * binom_basis(pb->p, pb->degree));
+    const size_t np = k >= 4 ? 16 * class_tiles(k) : std::max(16, 8 << k);
+    return b + cells * np * np * sizeof(double);
+  }
   for (size_t c = 0; c < cells; ++c) {
     const int dg = pb->cell_degree ? pb->cell_degree[c] : pb->degree;
     const int n = M * binom_basis(pb->p, dg);
@@ -1287,7 +1295,17 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   if (pb->n_retard > 0) ALLOC(P.d_retard, sizeof(Retard));
   if (P.flux == IPM_FLUX_SG_ANALYTIC)
     ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
-  if (P.hessian_reuse) {
+  if (P.hessian_reuse && P.adapt) {
+    // one slot per cell, sized for the largest inexact-Hessian class
+    int npmax = 0;
+    for (DualClass& D : P.cls)
+      if (D.configured && (D.prec & 2)) npmax = std::max(npmax, D.NP);
+    if (npmax > 0) {
+      P.hinv_all_stride = static_cast<long long>(npmax) * npmax;
+      ALLOC(P.d_hinv_all, static_cast<size_t>(P.cells) * P.hinv_all_stride * sizeof(double));
+      ALLOC(P.d_hinv_ok, static_cast<size_t>(P.cells));
+    }
+  } else if (P.hessian_reuse) {
     // NP x NP doubles for the cells of each inexact-Hessian class only
     bool any = false;
     for (DualClass& D : P.cls)

@@ -69,6 +69,7 @@ struct UpdateParams {
   const Retard* retard;              // null: no level cap
   unsigned cls_map;                  // 4 bits per size class: the class whose lists take its cells
   const double* __restrict__ ctp;    // analytic SG flux: [N][N][N] <phi_i phi_a phi_b> (else null)
+  unsigned char* __restrict__ hinv_ok;  // adaptive inexact-Hessian Newton: stored inverses (else null)
 };
 
 // index of the neighbour across side 0 (x-) or 1 (x+) of a 1D cell: the
@@ -284,6 +285,8 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
       if (P.retard) dn = min(dn, P.retard->deg[P.retard->stage]);  // Alg. adosIPM cap
       Nn = basis_count(P.p, dn);
       if (r == 0) P.cellN_next[cell] = static_cast<int8_t>(Nn);
+      // a stored inverse Hessian belongs to the cell's old level
+      if (Nn != Nc && P.hinv_ok != nullptr && r == 0) P.hinv_ok[cell] = 0;
       if (Nn < Nc) {
         lowered = true;
         for (int k = r; k < M * N; k += G) {
