@@ -406,9 +406,16 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
       // area when there is one
       const size_t extra = ((D.prec & 2) && !(D.prec & 1)) ? sizeof(double) * 17 * 16 * D.T : 0;
       D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true) + extra;
-      if ((D.prec & 1) && D.lds > ctx->max_lds) {  // build the B fragments on the fly instead
-        D.bcache = 0;
-        D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false) + extra;
+      if (D.prec & 1) {
+        // build the B fragments on the fly instead of caching them when the
+        // cache does not fit, or when it would cost the second workgroup
+        // per CU that the registers allow (160 KiB of LDS per CU)
+        const size_t lean = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false) + extra;
+        const size_t cu = 160 * 1024;
+        if (D.lds > ctx->max_lds || (2 * D.lds > cu && 2 * lean <= cu)) {
+          D.bcache = 0;
+          D.lds = lean;
+        }
       }
     }
     if (D.lds > ctx->max_lds)
