@@ -77,7 +77,11 @@ enum { IPM_ENT_QUADRATIC = 0, IPM_ENT_LOG_BARRIER = 1, IPM_ENT_EULER = 2 };
 enum { IPM_FLUX_LF = 0, IPM_FLUX_RUSANOV = 1, IPM_FLUX_SG_ANALYTIC = 2 };
 enum { IPM_BC_OUTFLOW = 0, IPM_BC_PERIODIC = 1, IPM_BC_DIRICHLET = 2 };
 /* arithmetic of the Hessian assembly (Newton update, Cholesky solve, gradient
-   and the tau test are always FP64) */
+   and the tau test are always FP64).  IPM_PREC_BF16: split-BF16 products on
+   the matrix cores for cells of 65..96 unknowns; smaller cells (register-row
+   kernels) and larger ones (whose FP32 block area would cost occupancy)
+   keep the FP64 assembly.  IPM_PREC_FP32 is rejected (no faster than FP64
+   here). */
 enum { IPM_PREC_FP64 = 0, IPM_PREC_FP32 = 1, IPM_PREC_BF16 = 2 };
 /* quadrature rule for xi ~ U(-1,1)^p (Sec. 3.1 <.>_Q; Sec. 7 compares
    tensorized and sparse Clenshaw-Curtis grids): tensor Gauss-Legendre or

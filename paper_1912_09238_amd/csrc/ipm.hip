@@ -346,7 +346,10 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
         return fail(ctx, IPM_E_ARG, "m*N = " + std::to_string(n) + " unknowns per cell exceeds 144");
       D.T = class_tiles(c);
       D.NP = 16 * D.T;
-      D.prec = (P.precision == IPM_PREC_BF16 ? 1 : 0) | (P.hessian_reuse ? 2 : 0);
+      // BF16 Hessian up to 96 unknowns: above, its FP32 block area (92 KB
+      // at 140 unknowns and 125 nodes) costs more occupancy than the MFMA
+      // saves (measured 0.76x the FP64 assembly there)
+      D.prec = (P.precision == IPM_PREC_BF16 && D.T <= 6 ? 1 : 0) | (P.hessian_reuse ? 2 : 0);
     } else {
       D.NP = 8 << c;
       // no BF16 Hessian below 65 unknowns; inexact-Hessian Newton on the
