@@ -282,9 +282,11 @@ ipm_status ipm_serve(ipm_ctx *ctx, int n, ipm_request *reqs, int steps_per_round
 
 /* Autotuner of the batched launches (no passage of the paper: a launch-shape
    choice).  For every small-cell Newton kernel shape among the problems, runs
-   1 + steps_per_candidate real time steps of all n_ids problems with 1, 2 and
-   4 wavefronts per block, keeps the fastest and remembers it for problems of
-   the same shape created later in this context.  The choice does not change
+   1 + steps_per_candidate real time steps of all n_ids problems with 1, 2,
+   4, 4, 2 and 1 wavefronts per block (mirrored, so that the drift of the work
+   per step cancels), keeps the shape of the smallest total time (the planned
+   shape unless another is more than 3 % faster) and remembers it for
+   problems of the same shape created later in this context.  The choice does not change
    any result (each cell's arithmetic is independent of the block shape); the
    timed steps advance the problems.  *n_tuned (nullable) = shapes tuned. */
 ipm_status ipm_autotune(ipm_ctx *ctx, int n_ids, const int *ids, int steps_per_candidate,
