@@ -45,6 +45,13 @@ template <int M, int T, int PREC = 0>
 struct BigCfg {
   static_assert(16 % M == 0, "tile variables need M | 16");
   static constexpr int NPB = 16 * T;  // unknowns incl. identity padding
+  // 16-mode tiles of one variable's block: the class's cells have at most
+  // 16 T / M modes, whatever the problem's widest cell
+  static constexpr int NTMAX = (16 * T / M + 15) / 16;
+  __host__ __device__ static int block_tiles(int kp) {
+    const int nt = (kp + 15) / 16;
+    return nt < NTMAX ? nt : NTMAX;
+  }
   static constexpr int NJ = M * (M + 1) / 2;
   // inexact-Hessian Newton: right-hand side [NPB] and row partial sums
   // [16][NPB] of the product with the stored inverse, after the rest
@@ -56,8 +63,9 @@ struct BigCfg {
                                  static_cast<size_t>(Q) * (M + NJ) + 2 * NPB + 2 + 32);
     if (PREC & 1) {
       // FP32 blocks [NJ][16 NT][16 NT] and BF16 hi/lo B fragments
-      // [NT][QC][64 lanes][16], NT = ceil(N / 16), QC = ceil(Q / 32), N <= kp
-      const size_t nt = (kp + 15) / 16, qc = (Q + 31) / 32;
+      // [NT][QC][64 lanes][16], NT = ceil(N / 16) for the class's widest
+      // cell, QC = ceil(Q / 32)
+      const size_t nt = block_tiles(kp), qc = (Q + 31) / 32;
       b += sizeof(float) * NJ * (16 * nt) * (16 * nt) + (bcache ? 32 * 64 * nt * qc : 0);
     }
     return b;
@@ -116,7 +124,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   for (int k = tid; k < Q * kp; k += 256) phiL[k] = P.phi[k];
   for (int q = tid; q < Q; q += 256) wL[q] = P.wphi[static_cast<size_t>(q) * kp];
   // precision form: FP32 Hessian blocks and the constant B fragments phi_k(q)
-  const int NT = (kp + 15) / 16, QC = (Q + 31) / 32, S16 = 16 * NT;
+  const int NT = Cfg::block_tiles(kp), QC = (Q + 31) / 32, S16 = 16 * NT;
   float* Hb = reinterpret_cast<float*>(red + 32);                        // [NJ][S16][S16]
   bf16x8* Bf = reinterpret_cast<bf16x8*>(Hb + static_cast<size_t>(NJ) * S16 * S16);  // [NT][QC][2][64]
   // B fragment f = K QC + c of this lane: phi_k(q) for its column k and 8 nodes
