@@ -275,9 +275,8 @@ __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lam
 
 // Layout: a group of G = NP / R lanes owns one cell, 64 / G cells per
 // wavefront, up to four wavefronts per block.  Lane r of a group holds the R
-// Hessian rows r, r + G, ... (all NP columns each) and the matching unknowns.
-// With R = 2 every pivot-column value read from LDS feeds two rows, which
-// halves the LDS traffic of the elimination (the kernel is LDS-bound).
+// Hessian rows r, r + G, ... (all NP columns each) and the matching unknowns;
+// R = 1 (one row per lane) in every configuration built.
 // Control flow is uniform within a group; groups of one wavefront may leave
 // the Newton loop at different iterations (cross-lane operations stay inside
 // the group).
