@@ -6,8 +6,9 @@
 // lists the cells that need Newton steps in 64 lists; the other cells keep
 // their dual and nodal ansatz unchanged, exactly as a solve that stops at
 // iteration 0 would.
-//  * newton_kernel: one wavefront per listed cell (or per cell in one-shot
-//    and setup runs) iterates Newton to tau:
+//  * newton_kernel: one group of NP lanes per listed cell (NP = n rounded up
+//    to 8, 16, 32 or 64; or per cell in one-shot and setup runs) iterates
+//    Newton to tau:
 //      - unknowns interleaved r = i*m + a (mode i, variable a), so a lower
 //        degree is a prefix;
 //      - ansatz: lanes over nodes, u_s and the packed grad u_s to LDS;
@@ -17,26 +18,29 @@
 //        accumulates row r in registers;
 //      - H d = g: Gauss-Jordan elimination without pivoting (H is SPD).
 //        Rows and columns beyond the cell's n unknowns are an identity
-//        block, so every pivot step runs unconditionally.  At each step all
-//        rows publish their entry in the pivot column through LDS; by
-//        symmetry of the Schur complement this column is also the pivot row,
-//        so every row is updated from it, the right-hand side is eliminated
-//        along, and no back-substitution (no transposed access) is needed;
+//        block.  At each step every row needs the pivot column (16 and 32
+//        lanes: DPP row broadcasts plus a 16-lane row swap, register to
+//        register; 8 and 64 lanes: through LDS); by symmetry of the Schur
+//        complement this column is also the pivot row, so every row is
+//        updated from it, the right-hand side is eliminated along, and no
+//        back-substitution (no transposed access) is needed;
 //      - step length: Armijo backtracking on L when the dual residual
 //        exceeds 1e-6, else the full step; one-shot: one full step;
 //      - inexact-Hessian variant (PREC bit 1; the outlook of Sec. 7 on not
 //        recomputing the Hessian): a fresh Hessian is inverted in place by
 //        the symmetric sweep (the matrix stays symmetric, so the broadcast
-//        pivot column again serves as the pivot row), the cell's n x n block
-//        of -H^-1 goes to HBM, and later iterations of the cell, in this and following
-//        steps, take d = H_old^-1 g from them while each such step
-//        contracts the dual residual by a factor theta; otherwise the inverse is retired and the
-//        next iteration (one-shot: of the next pseudo-time step) assembles
-//        and inverts afresh.  The tau test is unchanged.
+//        pivot column again serves as the pivot row), the cell's n x n
+//        block of -H^-1 goes to HBM, and later iterations of the cell, in
+//        this and following steps, take d = H_old^-1 g from it while each
+//        such step contracts the dual residual by a factor theta; otherwise
+//        the inverse is retired and the next iteration (one-shot: of the
+//        next pseudo-time step) assembles and inverts afresh.  The tau test
+//        is unchanged.
 // The dual, the nodal ansatz (read by the flux update) and the wave speeds
-// leave the kernels; the Hessian never touches HBM.  Statistics go to
-// per-block cumulative counters (plain stores) and to 64 atomic speed slots
-// on separate cache lines; no device-scope fence is issued.
+// leave the kernels; the exact variant's Hessian never touches HBM.
+// Statistics go to per-block cumulative counters (plain stores) and to 64
+// atomic speed slots on separate cache lines; no device-scope fence is
+// issued.
 #pragma once
 
 #include <type_traits>
