@@ -1,7 +1,8 @@
 """Independent NumPy references used to pin the oracle (test code only).
 
 - deterministic finite-volume solvers (Burgers / Lax-Friedrichs, 1D Euler /
-  Rusanov) advancing many samples with a shared or a per-sample time step:
+  Rusanov, 2D Euler / Rusanov or Lax-Friedrichs on a Cartesian grid) advancing
+  many samples with a shared or a per-sample time step:
   the special cases N = 1 (deterministic FV) and N = Q (coupled collocation);
 - the stochastic-Galerkin Burgers flux with triple products (App. A,
   eq:numFluxAnalytic), with its own high-order quadrature;
@@ -80,6 +81,78 @@ def fv_euler_rusanov(U, dx, cfl, t_end=None, steps=None):
         s = np.maximum(ag[:-1], ag[1:])[..., None]
         g = 0.5 * (fg[:-1] + fg[1:]) - 0.5 * s * (Ug[1:] - Ug[:-1])
         U = U - dt / dx * (g[1:] - g[:-1])
+        t = t_end if last else t + dt
+        k += 1
+    return U, k
+
+
+# ---------------------------------------------------------------- Euler 2D
+def euler_flux_2d(U, direction):
+    """Physical flux of the 2D Euler equations in x (direction 0) or y (1) and
+    the wave speed |v_n| + c in that direction.  U[..., 4] = (rho, m_x, m_y, E)."""
+    rho, mx, my, E = U[..., 0], U[..., 1], U[..., 2], U[..., 3]
+    vx, vy = mx / rho, my / rho
+    p = (GAMMA - 1) * (E - 0.5 * rho * (vx * vx + vy * vy))
+    c = np.sqrt(GAMMA * p / rho)
+    vn = vx if direction == 0 else vy
+    f = np.stack([rho * vn, mx * vn + (p if direction == 0 else 0.0),
+                  my * vn + (p if direction == 1 else 0.0), (E + p) * vn], axis=-1)
+    return f, np.abs(vn) + c
+
+
+def _pad_axis(U, axis, lo_periodic, hi_periodic):
+    """One ghost layer on each end of `axis`: periodic wrap or outflow copy."""
+    n = U.shape[axis]
+    lo = np.take(U, [n - 1 if lo_periodic else 0], axis=axis)
+    hi = np.take(U, [0 if hi_periodic else n - 1], axis=axis)
+    return np.concatenate([lo, U, hi], axis=axis)
+
+
+def fv_euler2d(U, dx, dy, cfl, bc, flux="rusanov", t_end=None, steps=None):
+    """Deterministic 2D Euler finite volumes for S samples sharing one time step
+    (coupled collocation); S = 1 is the plain deterministic scheme.
+
+    U: [ny][nx][S][4], cell (iy, ix).  bc: 4 sides (x-, x+, y-, y+), each
+    "periodic" or "outflow" (ghost = the boundary cell).  Unsplit update with
+    the normal flux on each of the four faces; per face either Rusanov
+    (viscosity 0.5 max(|v_n|+c) of the two states) or Lax-Friedrichs
+    (viscosity h/(2 dt), h the cell width across the face).  Time step
+    dt = cfl / (a_x/dx + a_y/dy) with a_x, a_y the largest |v_x|+c, |v_y|+c
+    over all cells and samples, the last step clipped to t_end.
+    Returns (U, steps taken)."""
+    U = np.array(U, dtype=np.float64)
+    per = [b == "periodic" for b in bc]
+    t, k = 0.0, 0
+    while True:
+        if steps is not None and k >= steps:
+            break
+        if t_end is not None and t >= t_end:
+            break
+        _, ax = euler_flux_2d(U, 0)
+        _, ay = euler_flux_2d(U, 1)
+        dt = cfl / (ax.max() / dx + ay.max() / dy)
+        if not np.isfinite(dt) or dt <= 0.0:
+            raise FloatingPointError("fv_euler2d: non-finite state at step %d" % k)
+        last = False
+        if t_end is not None and t + dt >= t_end:
+            dt, last = t_end - t, True
+        # x faces: pad along axis 1 (ix)
+        Ux = _pad_axis(U, 1, per[0], per[1])
+        fx, sx = euler_flux_2d(Ux, 0)
+        if flux == "rusanov":
+            vx = 0.5 * np.maximum(sx[:, :-1], sx[:, 1:])[..., None]
+        else:
+            vx = dx / (2 * dt)
+        Gx = 0.5 * (fx[:, :-1] + fx[:, 1:]) - vx * (Ux[:, 1:] - Ux[:, :-1])
+        # y faces: pad along axis 0 (iy)
+        Uy = _pad_axis(U, 0, per[2], per[3])
+        fy, sy = euler_flux_2d(Uy, 1)
+        if flux == "rusanov":
+            vy = 0.5 * np.maximum(sy[:-1], sy[1:])[..., None]
+        else:
+            vy = dy / (2 * dt)
+        Gy = 0.5 * (fy[:-1] + fy[1:]) - vy * (Uy[1:] - Uy[:-1])
+        U = U - dt / dx * (Gx[:, 1:] - Gx[:, :-1]) - dt / dy * (Gy[1:] - Gy[:-1])
         t = t_end if last else t + dt
         k += 1
     return U, k

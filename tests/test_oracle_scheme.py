@@ -90,6 +90,62 @@ def test_n_equals_q_is_coupled_collocation(orc, case):
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-9
 
 
+# ---------------------------------------------------------------- P2, P3 in 2D
+def _bump_nonsquare(degree, qpd, p, bc):
+    """2D Euler bump on a non-square grid (30 x 20 cells on [0,1] x [0,0.5]:
+    dx = 1/30 != dy = 1/40), off-centre, moving with v = (1, 0.5), with a
+    deterministic amplitude so that the single node xi = 0 sees a bump."""
+    spec = W.bump2d(n=30, degree=degree, qpd=qpd, p=p, t_end=0.08, center=(0.62, 0.38),
+                    amp0=0.5)
+    spec["ny"], spec["y1"], spec["bc"] = 20, 0.5, bc
+    spec["tau"] = 1e-12
+    return spec
+
+
+BC2D = [("periodic",) * 4, ("periodic", "periodic", "outflow", "outflow"),
+        ("outflow", "outflow", "periodic", "periodic")]
+
+
+@pytest.mark.parametrize("bc", BC2D)
+def test_single_basis_function_is_deterministic_fv_euler2d(orc, bc):
+    """N = 1 in 2D (degree 0, one node at xi = 0): the unsplit five-point
+    update (reading C14 of Sec. 3.1 eq:momentIterationFunction on a
+    Cartesian grid) with per-face Rusanov fluxes and the 2D time step
+    dt = CFL / (a_x/dx + a_y/dy) (reading C9) is the deterministic finite-volume
+    scheme of an independent NumPy solver: same step count, states to 1e-12.
+    The grid has dx != dy and the flow v_x != v_y, so exchanging dx and dy in
+    the update or the time step, or taking v_x for v_y in the y flux, moves the
+    reference by 2e-2 to 7e-2 and fails the pin."""
+    spec = _bump_nonsquare(0, 1, 2, bc)
+    o = _oracle(orc, spec)
+    info = o.run()
+    assert info["status"] == 0
+    U0 = W.ic_nodal(spec, np.zeros((1, 2))).reshape(20, 30, 1, 4)
+    ref, k = refs.fv_euler2d(U0, 1.0 / 30, 0.5 / 20, 0.5, bc, t_end=0.08)
+    assert k == info["steps"] and k > 10
+    got = o.moments()[:, :, 0].reshape(20, 30, 4)
+    assert np.max(np.abs(got - ref[:, :, 0, :])) < 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("bc", BC2D[:2])
+def test_n_equals_q_is_coupled_collocation_euler2d(orc, bc):
+    """N = Q in 2D (one uncertainty, degree 3, 4 Gauss nodes): Phi is square,
+    so the nodal values of the IPM moments evolve as four deterministic 2D
+    solves sharing one time step (the largest speed over all of them), for
+    the Euler entropy; same non-square grid and flow as the N = 1 pin."""
+    spec = _bump_nonsquare(3, 4, 1, bc)
+    o = _oracle(orc, spec)
+    nod0 = W.ic_nodal(spec, o.nodes)
+    info = o.run()
+    assert info["status"] == 0
+    _, _, Phi = o.tables()
+    got = np.einsum("qi,cai->cqa", Phi, o.moments()).reshape(20, 30, 4, 4)
+    ref, k = refs.fv_euler2d(nod0.reshape(20, 30, 4, 4), 1.0 / 30, 0.5 / 20, 0.5, bc,
+                             t_end=0.08)
+    assert k == info["steps"]
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-11
+
+
 # ---------------------------------------------------------------- P6
 def test_conservation_up_to_boundary_flux_sod(orc):
     spec = W.sod(nx=64, degree=4, qpd=8, spread=0.05)
