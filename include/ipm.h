@@ -253,6 +253,27 @@ ipm_status ipm_set_problem(ipm_ctx *ctx, const ipm_problem *pb, int *problem_id)
 ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
                     ipm_step_info *info);
 
+/* ipm_step for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same batched launches as ipm_step with two or more ids (one problem is
+   also allowed), launched one by one on the context's stream without a
+   graph, and the results equal ipm_step's bit for bit.  The launches'
+   parameter arrays and block offsets live in a fixed device array of
+   512 KiB per GPU (defined in the library, held until the process ends),
+   not in allocations of the call; ids whose arrays would exceed it (per
+   problem and step parity 232 bytes per Newton size class plus 368 for the
+   update: about 2.6 KB for a problem with four classes, so about 200 such
+   problems) fail with IPM_E_ARG and a message naming the size.  The problems' own state comes from ipm_set_problem as for
+   ipm_step.  Every call on a GPU shares that GPU's array, which keeps the
+   last call's contents: the first call for an id list (or after another
+   list, context or ipm_step has used the array or moved the problems)
+   uploads the arrays and waits for the stream once; later calls with the
+   same list launch at once.  Calls that overlap on one GPU (two contexts or
+   threads at the same time) race on the array and are not allowed.  Errors
+   as ipm_step; info as ipm_step (the call waits when info != NULL). */
+ipm_status ipm_step_static(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
+                           ipm_step_info *info);
+
 /* Static per-cell total degree for the batching form (Sec. 5: the first
    entry of the smoothness indicator eq:errorIndicator, computed from the
    first conserved variable's moments at t = 0).  Levels are total degrees

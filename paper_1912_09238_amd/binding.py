@@ -77,7 +77,7 @@ EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
            "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_cell_degrees",
-           "ipm_quadrature_size", "ipm_quadrature_rule", "ipm_last_error"]
+           "ipm_quadrature_size", "ipm_quadrature_rule", "ipm_last_error", "ipm_step_static"]
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load(path=None):
     lib.ipm_basis_table.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int]
     lib.ipm_set_problem.argtypes = [vp, P(Problem), ip]
     lib.ipm_step.argtypes = [vp, C.c_int, ip, C.c_int, P(StepInfo)]
+    lib.ipm_step_static.argtypes = [vp, C.c_int, ip, C.c_int, P(StepInfo)]
     lib.ipm_query.argtypes = [vp, C.c_int, P(StepInfo)]
     lib.ipm_moments.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
     lib.ipm_dual.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
@@ -306,6 +307,14 @@ class Context:
         arr = (C.c_int * len(ids))(*ids)
         infos = (StepInfo * len(ids))() if wait else None
         self._check(self.lib.ipm_step(self.h, len(ids), arr, int(max_steps), infos))
+        return [i.as_dict() for i in infos] if wait else None
+
+    def step_static(self, ids, max_steps, wait=False):
+        """ipm_step_static: the batched step without device allocations."""
+        ids = [ids] if isinstance(ids, int) else list(ids)
+        arr = (C.c_int * len(ids))(*ids)
+        infos = (StepInfo * len(ids))() if wait else None
+        self._check(self.lib.ipm_step_static(self.h, len(ids), arr, int(max_steps), infos))
         return [i.as_dict() for i in infos] if wait else None
 
     def query(self, pid):

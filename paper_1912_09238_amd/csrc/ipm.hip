@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -142,17 +143,38 @@ struct BatchPlan {
   size_t nd = 0, nu = 0;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool owned = true;  // false: the arrays live in the static scratch (not freed)
+  unsigned long long scratch_tag = 0;  // static plans: upload this plan's contents carry
   ~BatchPlan() {
     for (int k = 0; k < 2; ++k) {
       if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
       if (graph[k]) (void)hipGraphDestroy(graph[k]);
     }
+    if (!owned) return;
     if (d_dp) (void)hipFree(d_dp);
     if (d_up) (void)hipFree(d_up);
     if (d_begin) (void)hipFree(d_begin);
     if (d_dev_begin) (void)hipFree(d_dev_begin);
   }
 };
+
+// Device scratch of ipm_step_static: the batched launches' parameter arrays
+// and block offsets, for callers that cannot allocate.  One copy per GPU,
+// held until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// name is a host-side stand-in, not a device address).
+constexpr size_t kStaticScratchBytes = 512 * 1024;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Per device: the scratch's device address and which upload it holds.
+struct ScratchSlot {
+  unsigned char* ptr = nullptr;
+  const void* owner = nullptr;   // context whose plan the scratch holds
+  unsigned long long tag = 0;    // that upload
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+unsigned long long g_scratch_uploads = 0;
 
 }  // namespace
 
@@ -171,6 +193,13 @@ struct ipm_ctx {
   unsigned long long gen = 0;              // bumped when problems or launch shapes change
   std::unique_ptr<BatchPlan> batch;        // cached plan of the last batched ipm_step
   std::map<std::string, int> tuned_waves;  // autotuner: wavefronts per Newton block by shape
+  // ipm_step_static: this device's scratch address, the plan it stepped last
+  // and the host copies of that plan's arrays
+  unsigned char* scratch = nullptr;
+  std::unique_ptr<BatchPlan> static_plan;
+  std::vector<DualParams> static_dps;
+  std::vector<UpdateParams> static_ups;
+  std::vector<int> static_begins;
 };
 
 namespace {
@@ -663,11 +692,13 @@ const void* pick_update_batched(int M, int G) {
   return nullptr;
 }
 
-// Build the launch lists of both step parities for the problems `ids`
-// (their next step and the one after), upload the parameter arrays and
-// instantiate one graph per parity.
-ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out) {
-  auto B = std::make_unique<BatchPlan>();
+// Host part of a batch plan: the launch lists of both step parities for the
+// problems `ids` (their next step and the one after) and the parameter and
+// block-offset arrays the batched kernels read.
+ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
+                      std::vector<DualParams>& dps, std::vector<UpdateParams>& ups,
+                      std::vector<int>& begins) {
+  BatchPlan* B = &Bp;
   B->ids = ids;
   B->gen = ctx->gen;
   for (int id : ids) B->step0.push_back(get(ctx, id)->step_index);
@@ -681,9 +712,9 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
     int blocks;
     size_t lds;
   };
-  std::vector<DualParams> dps;
-  std::vector<UpdateParams> ups;
-  std::vector<int> begins;
+  dps.clear();
+  ups.clear();
+  begins.clear();
   for (int ph = 0; ph < 2; ++ph) {
     std::map<std::string, std::vector<NEntry>> ng;
     std::map<std::string, std::pair<int, int>> nshape;  // key -> (threads, M)
@@ -787,6 +818,18 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
   }
   B->nd = dps.size();
   B->nu = ups.size();
+  return IPM_OK;
+}
+
+// Build a batch plan in device buffers of its own: upload the parameter
+// arrays and instantiate one graph per parity.
+ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out) {
+  auto B = std::make_unique<BatchPlan>();
+  std::vector<DualParams> dps;
+  std::vector<UpdateParams> ups;
+  std::vector<int> begins;
+  ipm_status pst = plan_batch(ctx, ids, *B, dps, ups, begins);
+  if (pst != IPM_OK) return pst;
   HIPCHK(ctx, hipMalloc(&B->d_dp, std::max<size_t>(dps.size(), 1) * sizeof(DualParams)));
   HIPCHK(ctx, hipMalloc(&B->d_up, std::max<size_t>(ups.size(), 1) * sizeof(UpdateParams)));
   HIPCHK(ctx, hipMalloc(&B->d_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
@@ -872,6 +915,43 @@ bool batch_valid(const ipm_ctx* ctx, const BatchPlan* B, const std::vector<int>&
   return true;
 }
 
+// One batched step of phase ph launch by launch on the context's stream;
+// e (nullable): events around the Newton and the update phase.
+ipm_status launch_batch_step(ipm_ctx* ctx, const BatchPlan& B, int ph, hipEvent_t* e) {
+  if (e) HIPCHK(ctx, hipEventRecord(e[0], ctx->stream));
+  int phase_kind = 0;
+  for (const BatchLaunch& L : B.launches[ph]) {
+    if (L.kind != 0 && phase_kind == 0) {
+      if (e) {
+        HIPCHK(ctx, hipEventRecord(e[1], ctx->stream));
+        HIPCHK(ctx, hipEventRecord(e[2], ctx->stream));
+      }
+      phase_kind = 1;
+    }
+    if (L.kind == 0 || L.kind == 1) {
+      const void* pp = L.kind == 0 ? static_cast<const void*>(B.d_dp + L.pofs)
+                                   : static_cast<const void*>(B.d_up + L.pofs);
+      const int* bg = (L.kind == 0 && L.lists) ? B.d_dev_begin + L.bofs : B.d_begin + L.bofs;
+      int n = L.n;
+      if (L.kind == 0 && L.lists) {
+        hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(64), 0, ctx->stream,
+                           B.d_dp + L.pofs, n, L.per_block, B.d_dev_begin + L.bofs);
+        HIPCHK(ctx, hipGetLastError());
+      }
+      void* args[3] = {&pp, &bg, &n};
+      HIPCHK(ctx, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.threads), args, L.lds, ctx->stream));
+    } else {
+      const Problem& P = *get(ctx, L.pid);
+      hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
+                         P.upd_blocks, P.steady_eps, L.parity, P.d_blk, P.dual_blocks, 0,
+                         P.d_retard);
+      HIPCHK(ctx, hipGetLastError());
+    }
+  }
+  if (e) HIPCHK(ctx, hipEventRecord(e[3], ctx->stream));
+  return IPM_OK;
+}
+
 // `steps` batched steps: graph replays, or launch by launch with events
 // around the Newton and update phases when kernel timing is on
 ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
@@ -887,35 +967,8 @@ ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
       }
       hipEvent_t* e = &ctx->ev[ctx->ev_used];
       ctx->ev_used += 4;
-      HIPCHK(ctx, hipEventRecord(e[0], ctx->stream));
-      int phase_kind = 0;
-      for (const BatchLaunch& L : B.launches[ph]) {
-        if (L.kind != 0 && phase_kind == 0) {
-          HIPCHK(ctx, hipEventRecord(e[1], ctx->stream));
-          HIPCHK(ctx, hipEventRecord(e[2], ctx->stream));
-          phase_kind = 1;
-        }
-        if (L.kind == 0 || L.kind == 1) {
-          const void* pp = L.kind == 0 ? static_cast<const void*>(B.d_dp + L.pofs)
-                                       : static_cast<const void*>(B.d_up + L.pofs);
-          const int* bg = (L.kind == 0 && L.lists) ? B.d_dev_begin + L.bofs : B.d_begin + L.bofs;
-          int n = L.n;
-          if (L.kind == 0 && L.lists) {
-            hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(64), 0, ctx->stream,
-                               B.d_dp + L.pofs, n, L.per_block, B.d_dev_begin + L.bofs);
-            HIPCHK(ctx, hipGetLastError());
-          }
-          void* args[3] = {&pp, &bg, &n};
-          HIPCHK(ctx, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.threads), args, L.lds, ctx->stream));
-        } else {
-          const Problem& P = *get(ctx, L.pid);
-          hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
-                             P.upd_blocks, P.steady_eps, L.parity, P.d_blk, P.dual_blocks, 0,
-                             P.d_retard);
-          HIPCHK(ctx, hipGetLastError());
-        }
-      }
-      HIPCHK(ctx, hipEventRecord(e[3], ctx->stream));
+      ipm_status st = launch_batch_step(ctx, B, ph, e);
+      if (st != IPM_OK) return st;
     }
     ++B.steps_done;
     for (int id : B.ids) ++get(ctx, id)->step_index;
@@ -1165,6 +1218,20 @@ ipm_status ipm_create(const ipm_config* cfg, ipm_ctx** out) {
     ctx->max_lds = static_cast<size_t>(lds);
   (void)hipGetLastError();
   if (set_kernel_attributes(ctx.get()) != IPM_OK) return fail(nullptr, IPM_E_DEVICE, ctx->err);
+  {
+    // the static scratch's address on this device (current), once per device
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot& slot = g_scratch[cfg->device];
+    if (!slot.ptr) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(nullptr, IPM_E_DEVICE,
+                    std::string("ipm_create: static scratch address: ") + hipGetErrorString(e));
+      slot.ptr = static_cast<unsigned char*>(ptr);
+    }
+    ctx->scratch = slot.ptr;
+  }
   *out = ctx.release();
   return IPM_OK;
 }
@@ -1174,6 +1241,12 @@ ipm_status ipm_destroy(ipm_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->batch.reset();
+  ctx->static_plan.reset();
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot& slot = g_scratch[ctx->device];
+    if (slot.owner == ctx) slot.owner = nullptr;
+  }
   for (auto& p : ctx->problems) free_problem(p.get());
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -1584,6 +1657,83 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
       ipm_status st = enqueue_close(ctx, *get(ctx, ids[k]));
       if (st != IPM_OK) return st;
     }
+  if (info)
+    for (int k = 0; k < n_ids; ++k) {
+      ipm_status st = ipm_query(ctx, ids[k], &info[k]);
+      if (st != IPM_OK) return st;
+    }
+  return IPM_OK;
+}
+
+ipm_status ipm_step_static(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps,
+                           ipm_step_info* info) {
+  if (!ctx) return IPM_E_ARG;
+  if (n_ids < 1 || !ids || max_steps < 0)
+    return fail(ctx, IPM_E_ARG, "ipm_step_static: bad arguments");
+  for (int k = 0; k < n_ids; ++k)
+    if (!get(ctx, ids[k])) return fail(ctx, IPM_E_STATE, "ipm_step_static: unknown problem id");
+  std::vector<int> v(ids, ids + n_ids);
+  for (size_t a = 0; a < v.size(); ++a)
+    for (size_t b = a + 1; b < v.size(); ++b)
+      if (v[a] == v[b]) return fail(ctx, IPM_E_ARG, "ipm_step_static: repeated problem id");
+  if (!ctx->scratch) return fail(ctx, IPM_E_DEVICE, "ipm_step_static: no static scratch");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (max_steps > 0) {
+    bool current = ctx->static_plan && batch_valid(ctx, ctx->static_plan.get(), v);
+    if (current) {
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      const ScratchSlot& slot = g_scratch[ctx->device];
+      current = slot.owner == ctx && slot.tag == ctx->static_plan->scratch_tag;
+    }
+    if (!current) {
+      // plan on the host, then place its arrays in the scratch (no allocation)
+      auto B = std::make_unique<BatchPlan>();
+      B->owned = false;
+      ipm_status st = plan_batch(ctx, v, *B, ctx->static_dps, ctx->static_ups, ctx->static_begins);
+      if (st != IPM_OK) return st;
+      auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+      const size_t bdp = ctx->static_dps.size() * sizeof(DualParams);
+      const size_t bup = ctx->static_ups.size() * sizeof(UpdateParams);
+      const size_t bbg = ctx->static_begins.size() * sizeof(int);
+      const size_t o_up = up(bdp), o_bg = o_up + up(bup), o_dv = o_bg + up(bbg);
+      const size_t total = o_dv + up(bbg);
+      if (total > kStaticScratchBytes)
+        return fail(ctx, IPM_E_ARG,
+                    "ipm_step_static: the launch parameters of these problems need " +
+                        std::to_string(total) + " bytes, the static scratch holds " +
+                        std::to_string(kStaticScratchBytes));
+      unsigned char* base = ctx->scratch;
+      B->d_dp = reinterpret_cast<DualParams*>(base);
+      B->d_up = reinterpret_cast<UpdateParams*>(base + o_up);
+      B->d_begin = reinterpret_cast<int*>(base + o_bg);
+      B->d_dev_begin = reinterpret_cast<int*>(base + o_dv);
+      // stream-ordered after earlier work on this stream; the wait lets the
+      // host copies be reused by the next upload
+      if (bdp) HIPCHK(ctx, hipMemcpyAsync(B->d_dp, ctx->static_dps.data(), bdp, hipMemcpyHostToDevice, ctx->stream));
+      if (bup) HIPCHK(ctx, hipMemcpyAsync(B->d_up, ctx->static_ups.data(), bup, hipMemcpyHostToDevice, ctx->stream));
+      if (bbg) HIPCHK(ctx, hipMemcpyAsync(B->d_begin, ctx->static_begins.data(), bbg, hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ScratchSlot& slot = g_scratch[ctx->device];
+        slot.owner = ctx;
+        slot.tag = ++g_scratch_uploads;
+        B->scratch_tag = slot.tag;
+      }
+      ctx->static_plan = std::move(B);
+    }
+    BatchPlan& B = *ctx->static_plan;
+    for (int s = 0; s < max_steps; ++s) {
+      ipm_status st = launch_batch_step(ctx, B, static_cast<int>(B.steps_done & 1), nullptr);
+      if (st != IPM_OK) return st;
+      ++B.steps_done;
+      for (int id : B.ids) ++get(ctx, id)->step_index;
+    }
+    for (int k = 0; k < n_ids; ++k) {
+      ipm_status st = enqueue_close(ctx, *get(ctx, ids[k]));
+      if (st != IPM_OK) return st;
+    }
+  }
   if (info)
     for (int k = 0; k < n_ids; ++k) {
       ipm_status st = ipm_query(ctx, ids[k], &info[k]);
