@@ -9,7 +9,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import check_parity, parity
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -65,6 +65,7 @@ def _compare(ctx, orc, spec, chunks, cd=None, dirichlet=False):
                 info["steps"], np.bincount(od, minlength=spec["degree"] + 1),
                 np.array2string(err, precision=2)))
             assert np.all(err <= TOL), err
+            check_parity(ctx.moments(pid), o.moments(), TOL)
     finally:
         ctx.release(pid)
     return moved, info, oinfo

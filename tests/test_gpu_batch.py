@@ -9,7 +9,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import check_parity, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +85,7 @@ def test_batch_matches_oracle(gpu_ctx, orc):
         err = parity(gpu_ctx.moments(pid), o.moments())
         _say("  %s parity %s" % (spec["name"], np.array2string(err, precision=2)))
         assert np.all(err <= 1e-10), err
+        check_parity(gpu_ctx.moments(pid), o.moments(), 1e-10)
         gpu_ctx.release(pid)
 
 

@@ -1,0 +1,129 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times, against stored oracle results (tests/golden/make_fullsize.py
+writes them from the CPU oracle alone): moments element by element at a
+deterministic sample of cells.
+
+- Sod tube, 8192 cells, degree 9, 20 nodes: the whole trajectory to
+  t_end = 0.14 (Alg. 1), FP64 form.
+- 2D bump, 512 x 512 cells, degree 5, 8 x 8 nodes: 2 time steps in the FP64
+  form, and in the mixed-precision form (BF16 Hessian on the matrix cores +
+  inexact-Hessian Newton with stored FP64 inverses, FP64 tau test).
+- The 64-problem batch (three uncertainties, per-cell degrees 1-4, 5^3
+  nodes), all problems stepped together: 2 time steps, FP64 and mixed
+  precision, every problem checked.
+
+Bounds: FP64 form 1e-10 (norm, element and per-mode measures of
+conftest.check_parity); mixed precision: expectation and variance within
+1e-4 relative L1 and L2 (the precision form's stated bound) and the moments
+within 1e-8 (the inexact-Newton bound of the other reuse tests: both sides
+stop at the same tau; per-mode measure 1e-7, conftest.INEXACT_MODE_TOL)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_09238_amd import workloads as W
+
+from .conftest import INEXACT_MODE_TOL, check_parity
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+MIXED = dict(precision="bf16", hessian_reuse=2)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail("missing %s: run tests/golden/make_fullsize.py" % path)
+    return np.load(path)
+
+
+def _e_var_errors(got, ref):
+    E, E0 = got[:, :, 0], ref[:, :, 0]
+    V, V0 = np.sum(got[:, :, 1:] ** 2, axis=2), np.sum(ref[:, :, 1:] ** 2, axis=2)
+    rel = lambda a, b, o: np.linalg.norm((a - b).ravel(), o) / np.linalg.norm(b.ravel(), o)
+    return [rel(E, E0, 1), rel(E, E0, 2), rel(V, V0, 1), rel(V, V0, 2)]
+
+
+def test_sod_full_trajectory(gpu_ctx):
+    from paper_1912_09238_amd import binding
+    g = _golden("fullsize_sod8192_t014.npz")
+    spec = W.sod()
+    nodes, _ = binding.quadrature(1, 20)
+    _say("gpu case: sod 8192 cells to t_end = 0.14 (%d steps)" % int(g["steps"]))
+    pid = gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+    info = gpu_ctx.step(pid, 20000, wait=True)[0]
+    got = gpu_ctx.moments(pid)[g["cells"]]
+    gpu_ctx.release(pid)
+    assert info["status"] == 0 and info["done"] == 1
+    assert info["steps"] == int(g["steps"])
+    assert abs(info["t"] - float(g["t"])) <= 1e-14
+    check_parity(got, g["moments"], 1e-10, "sod 8192 t=0.14")
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_bump512_two_steps(gpu_ctx, form):
+    from paper_1912_09238_amd import binding
+    g = _golden("fullsize_bump512_2steps.npz")
+    spec = W.bump2d()
+    if form == "mixed":
+        spec.update(MIXED)
+    nodes, _ = binding.quadrature(2, 8)
+    _say("gpu case: bump 512^2, 2 steps, %s" % form)
+    pid = gpu_ctx.set_problem(spec, ic_nodal=W.ic_nodal(spec, nodes))
+    info = gpu_ctx.step(pid, 2, wait=True)[0]
+    got = gpu_ctx.moments(pid)[g["cells"]]
+    gpu_ctx.release(pid)
+    assert info["status"] == 0 and info["steps"] == 2
+    # inexact Newton moves the ansatz, hence the wave speed and the time
+    # step, within the tau-ball (a few 1e-12 relative)
+    assert abs(info["t"] - float(g["t"])) <= (1e-14 if form == "fp64" else 1e-10 * float(g["t"]))
+    if form == "fp64":
+        check_parity(got, g["moments"], 1e-10, "bump512 fp64")
+    else:
+        errs = _e_var_errors(got, g["moments"])
+        _say("  mixed: E L1 %.2e L2 %.2e Var L1 %.2e L2 %.2e" % tuple(errs))
+        assert max(errs) <= 1e-4
+        check_parity(got, g["moments"], 1e-8, "bump512 mixed", mode_tol=INEXACT_MODE_TOL)
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_batch64_two_steps(gpu_ctx, form):
+    from paper_1912_09238_amd import binding
+    g = _golden("fullsize_batch64_2steps.npz")
+    specs = W.batch_problems(count=64)
+    nodes, _ = binding.quadrature(3, 5)
+    _say("gpu case: 64-problem batch, 2 steps, %s" % form)
+    ids = []
+    try:
+        for spec in specs:
+            s = dict(spec, **MIXED) if form == "mixed" else spec
+            ids.append(gpu_ctx.set_problem(s, ic_nodal=W.ic_nodal(spec, nodes),
+                                           cell_degree=W.cell_degrees(spec)))
+        infos = gpu_ctx.step(ids, 2, wait=True)
+        worst = 0.0
+        for k, (pid, info) in enumerate(zip(ids, infos)):
+            assert info["status"] == 0 and info["steps"] == 2, (k, info)
+            tk = float(g["t%02d" % k])
+            assert abs(info["t"] - tk) <= (1e-14 if form == "fp64" else 1e-10 * tk), k
+            cells = g["cells%02d" % k]
+            got = gpu_ctx.moments(pid)[cells]
+            ref = g["moments%02d" % k]
+            if form == "fp64":
+                st = check_parity(got, ref, 1e-10, "batch problem %d" % k)
+            else:
+                errs = _e_var_errors(got, ref)
+                assert max(errs) <= 1e-4, (k, errs)
+                st = check_parity(got, ref, 1e-8, "batch problem %d mixed" % k,
+                                  mode_tol=INEXACT_MODE_TOL)
+            worst = max(worst, max(float(v.max()) for v in st.values()))
+        _say("  worst measure over the 64 problems: %.2e" % worst)
+    finally:
+        for pid in ids:
+            gpu_ctx.release(pid)

@@ -10,7 +10,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import INEXACT_MODE_TOL, check_parity, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +45,7 @@ def _run(ctx, orc, spec, steps):
     _say("  parity %s  E %.2e Var %.2e  newton gpu=%d oracle=%d" % (
         np.array2string(err, precision=2), e, v, info["newton_iters"], oinfo["newton_iters"]))
     assert np.all(err <= 1e-8), err
+    check_parity(got, want, 1e-8, mode_tol=INEXACT_MODE_TOL)
     assert e <= 1e-4 and v <= 1e-4
 
 
@@ -87,6 +88,7 @@ def test_reuse_uneven_degrees(gpu_ctx, orc, level, precision):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-8), err
+    check_parity(got, o.moments(), 1e-8, mode_tol=INEXACT_MODE_TOL)
 
 
 @pytest.mark.parametrize("case", ["sod_n30", "burgers_n5", "burgers_n10", "bump_n24", "bump_n40"])
@@ -143,6 +145,7 @@ def test_reuse_one_shot_steady(gpu_ctx, orc):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-7), err
+    check_parity(got, o.moments(), 1e-7, mode_tol=INEXACT_MODE_TOL)
 
 
 def test_reuse_small_batched_equals_alone(gpu_ctx):
@@ -241,6 +244,7 @@ def test_reuse_with_adaptive_levels(gpu_ctx, orc, level, precision, p):
     if flips == 0:
         err = parity(got, want)
         assert np.all(err <= 1e-8), err
+        check_parity(got, want, 1e-8, mode_tol=INEXACT_MODE_TOL)
 
 
 def test_reuse_stricter_contraction(gpu_ctx, orc):

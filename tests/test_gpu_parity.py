@@ -9,7 +9,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import check_parity, parity
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -52,6 +52,7 @@ def _check(info, got, oinfo, o, tol=TOL):
     _say("  parity per variable: %s  newton gpu=%d oracle=%d" % (
         np.array2string(err, precision=2), info["newton_iters"], oinfo["newton_iters"]))
     assert np.all(err <= tol), err
+    check_parity(got, o.moments(), tol)
 
 
 def test_burgers_shock_full_run(gpu_ctx, orc):
@@ -114,7 +115,7 @@ def test_steady_dirichlet_one_shot(gpu_ctx, orc, one_shot):
     spec = W.steady_inflow(one_shot=one_shot)
     info, got, _, oinfo, o = _run_both(gpu_ctx, orc, spec, 5000, dirichlet=True)
     assert info["done"] == 1 and info["residual"] <= 1e-10
-    _check(info, got, oinfo, o, tol=1e-9)
+    _check(info, got, oinfo, o)
     want = np.zeros(5)
     want[0], want[1] = 1.0, 0.2 / math.sqrt(3.0)
     assert np.max(np.abs(got[:, 0, :] - want)) < 5e-8

@@ -10,6 +10,8 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
+from .conftest import INEXACT_MODE_TOL, check_parity
+
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
@@ -51,7 +53,11 @@ def _run(gpu_ctx, orc, spec, steps, cell_degree=None):
         errs = [_rel(E, E0, 1), _rel(E, E0, 2), _rel(V, V0, 1), _rel(V, V0, 2)]
         _say("  %s: E L1 %.2e L2 %.2e  Var L1 %.2e L2 %.2e  newton %d (oracle %d)" % (
             prec, *errs, info["newton_iters"], oinfo["newton_iters"]))
-        assert max(errs) <= (1e-9 if prec == "fp64" else TOL), (prec, errs)
+        assert max(errs) <= TOL, (prec, errs)
+        # FP64 form: the plain bound; BF16 Hessian: an inexact Newton that
+        # stops at the same FP64 tau, so the moments stay close as well
+        check_parity(mom, ref, 1e-10 if prec == "fp64" else 1e-8, prec,
+                     mode_tol=None if prec == "fp64" else INEXACT_MODE_TOL)
     return out
 
 

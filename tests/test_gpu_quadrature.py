@@ -7,7 +7,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import check_parity, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +34,7 @@ def _run(ctx, orc, spec, steps):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-10), err
+    check_parity(got, o.moments(), 1e-10)
 
 
 def test_sod_tensor_clenshaw_curtis(gpu_ctx, orc):

@@ -1,13 +1,18 @@
 """GPU: the serving loop (ipm_serve).  Requests of different sizes and orders
 arrive over time, are admitted by slot and HBM footprint, run as one batch
 while they overlap, and leave when done.  Each result must equal the same
-problem stepped alone (bitwise: batching changes no arithmetic)."""
+problem stepped alone (bitwise: batching changes no arithmetic) and the CPU
+oracle's result for the request (FP64 form: 1e-10 in the norm, element and
+per-mode measures; reduced forms: expectation and variance within 1e-4 and
+the moments within the inexact-Newton bound 1e-8)."""
 import sys
 
 import numpy as np
 import pytest
 
 from paper_1912_09238_amd import workloads as W
+
+from .conftest import INEXACT_MODE_TOL, check_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +53,22 @@ def _alone(ctx, rq):
     return info, mom
 
 
-def test_served_results_equal_alone(gpu_ctx):
+def _oracle_result(orc, rq):
+    spec = rq["spec"]
+    o = orc.Oracle(spec, ic_fn=lambda nd: W.ic_nodal(spec, nd))
+    info = o.run()
+    assert info["status"] == 0 and info["done"] == 1, info
+    return info, o.moments()
+
+
+def _e_var_errors(got, ref):
+    E, E0 = got[:, :, 0], ref[:, :, 0]
+    V, V0 = np.sum(got[:, :, 1:] ** 2, axis=2), np.sum(ref[:, :, 1:] ** 2, axis=2)
+    rel = lambda a, b, o: np.linalg.norm((a - b).ravel(), o) / np.linalg.norm(b.ravel(), o)
+    return [rel(E, E0, 1), rel(E, E0, 2), rel(V, V0, 1), rel(V, V0, 2)]
+
+
+def test_served_results_equal_alone(gpu_ctx, orc):
     reqs = _requests()
     _say("gpu case: serve %d requests, rounds of 4 steps, 4 active" % len(reqs))
     res = gpu_ctx.serve(reqs, steps_per_round=4, max_active=4)
@@ -59,6 +79,9 @@ def test_served_results_equal_alone(gpu_ctx):
         info, mom = _alone(gpu_ctx, rq)
         assert r["steps"] == info["steps"]
         assert np.array_equal(r["moments"], mom), (k, np.max(np.abs(r["moments"] - mom)))
+        oinfo, ref = _oracle_result(orc, rq)
+        assert r["steps"] == oinfo["steps"], k
+        check_parity(r["moments"], ref, 1e-10, "request %d" % k)
         overlap = max(overlap, sum(1 for s in res if s["admitted"] < r["finished"] <= s["finished"]))
     assert overlap >= 2  # requests really shared the device
 
@@ -91,7 +114,7 @@ def test_admission_by_hbm_footprint():
         assert sum(fps[j] for j in live) <= budget, (k, live)
 
 
-def test_served_mixed_precision_2d_equals_alone(gpu_ctx):
+def test_served_mixed_precision_2d_equals_alone(gpu_ctx, orc):
     """2D requests in the mixed-precision form (BF16 Hessian + inverse
     reuse): served in a mix, each equals the same problem stepped alone."""
     from paper_1912_09238_amd import binding
@@ -108,9 +131,15 @@ def test_served_mixed_precision_2d_equals_alone(gpu_ctx):
         info, mom = _alone(gpu_ctx, rq)
         assert r["steps"] == info["steps"]
         assert np.array_equal(r["moments"], mom), k
+        oinfo, ref = _oracle_result(orc, rq)
+        assert r["steps"] == oinfo["steps"], k
+        errs = _e_var_errors(r["moments"], ref)
+        assert max(errs) <= 1e-4, (k, errs)
+        check_parity(r["moments"], ref, 1e-8, "2D request %d mixed" % k,
+                     mode_tol=INEXACT_MODE_TOL)
 
 
-def test_served_inexact_hessian_1d_equals_alone(gpu_ctx):
+def test_served_inexact_hessian_1d_equals_alone(gpu_ctx, orc):
     """1D requests in the reduced-precision request form (inverse reuse on
     every cell; the stored inverses stay with each resident problem): served
     in a mix, each equals the same problem stepped alone."""
@@ -125,3 +154,9 @@ def test_served_inexact_hessian_1d_equals_alone(gpu_ctx):
         info, mom = _alone(gpu_ctx, rq)
         assert r["steps"] == info["steps"]
         assert np.array_equal(r["moments"], mom), k
+        oinfo, ref = _oracle_result(orc, rq)
+        assert r["steps"] == oinfo["steps"], k
+        errs = _e_var_errors(r["moments"], ref)
+        assert max(errs) <= 1e-4, (k, errs)
+        check_parity(r["moments"], ref, 1e-8, "1D request %d reuse" % k,
+                     mode_tol=INEXACT_MODE_TOL)

@@ -8,7 +8,7 @@ import pytest
 
 from paper_1912_09238_amd import workloads as W
 
-from .conftest import parity
+from .conftest import check_parity, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +46,7 @@ def test_analytic_sg_flux_vs_oracle(gpu_ctx, orc, bc):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-10), err
+    check_parity(got, o.moments(), 1e-10)
 
 
 def test_analytic_equals_kinetic_flux_on_the_gpu(gpu_ctx):
@@ -85,6 +86,7 @@ def test_sg_sod_realizability(gpu_ctx, orc):
     err = parity(got, o.moments())
     _say("  parity %s" % np.array2string(err, precision=2))
     assert np.all(err <= 1e-10), err
+    check_parity(got, o.moments(), 1e-10)
 
 
 @pytest.mark.parametrize("bad", [dict(entropy="log_barrier", u_minus=0.5, u_plus=2.5),
