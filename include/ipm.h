@@ -347,6 +347,41 @@ ipm_status ipm_release(ipm_ctx *ctx, int id);
 ipm_status ipm_kernel_timing(ipm_ctx *ctx, int enable, double *dual_ms, double *update_ms,
                              long long *launches);
 
+/* Device time of the batched Newton launches of the last timing window
+   (ipm_kernel_timing enable = 1 ... enable = 0; batched ipm_step only, which
+   then launches one kernel at a time): per kernel shape, the launches and
+   their summed milliseconds.  Measurement helper, no passage of the paper. */
+typedef struct {
+  int m;          /* conserved variables of the kernel */
+  int lanes;      /* register-row kernel: lanes per cell; workgroup kernel: 16 T rows */
+  int workgroup;  /* 1: one workgroup per cell (T x T register tiles), 0: register rows */
+  int variant;    /* bit 0: BF16 MFMA Hessian; bit 1: stored inverse Hessians */
+  int threads;    /* threads per block */
+  long long launches;
+  double ms;
+} ipm_launch_time;
+ipm_status ipm_launch_times(ipm_ctx *ctx, ipm_launch_time *out, int cap, int *n);
+
+/* Newton counters of a problem per size class (cumulative since set-up;
+   waits for the context's stream): the kernel shape of the class's launches,
+   the range of unknowns n = m N of the cells they solve, the class's cells,
+   and how many cells the launches solved (listed), their Newton iterations
+   (eq:dualIterationFunction steps) and how many of these assembled a fresh
+   Hessian (the rest reused a stored inverse).  *n = classes reported (at
+   most cap are written).  Measurement helper. */
+typedef struct {
+  int size_class;
+  int workgroup;  /* as in ipm_launch_time */
+  int lanes;
+  int variant;
+  int n_min, n_max;
+  long long cells;
+  long long listed;
+  long long iterations;
+  long long fresh;
+} ipm_class_stat;
+ipm_status ipm_class_stats(ipm_ctx *ctx, int id, ipm_class_stat *out, int cap, int *n);
+
 /* Message of the last failing call on ctx (owned by ctx, valid until the
    next call).  ctx may be NULL for errors of ipm_create. */
 const char *ipm_last_error(const ipm_ctx *ctx);

@@ -66,6 +66,24 @@ class StepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LaunchTime(C.Structure):
+    _fields_ = [("m", C.c_int), ("lanes", C.c_int), ("workgroup", C.c_int), ("variant", C.c_int),
+                ("threads", C.c_int), ("launches", C.c_longlong), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ClassStat(C.Structure):
+    _fields_ = [("size_class", C.c_int), ("workgroup", C.c_int), ("lanes", C.c_int),
+                ("variant", C.c_int), ("n_min", C.c_int), ("n_max", C.c_int),
+                ("cells", C.c_longlong), ("listed", C.c_longlong),
+                ("iterations", C.c_longlong), ("fresh", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Request(C.Structure):
     _fields_ = [("problem", C.c_void_p), ("arrival_s", C.c_double),
                 ("moments_out", C.POINTER(C.c_double)), ("moments_len", C.c_size_t),
@@ -77,7 +95,8 @@ EXPORTS = ["ipm_create", "ipm_destroy", "ipm_quadrature", "ipm_basis_size", "ipm
            "ipm_set_problem", "ipm_step", "ipm_query", "ipm_moments", "ipm_dual",
            "ipm_problem_sizes", "ipm_problem_footprint", "ipm_release", "ipm_kernel_timing",
            "ipm_select_degrees", "ipm_serve", "ipm_autotune", "ipm_cell_degrees",
-           "ipm_quadrature_size", "ipm_quadrature_rule", "ipm_last_error", "ipm_step_static"]
+           "ipm_quadrature_size", "ipm_quadrature_rule", "ipm_last_error", "ipm_step_static",
+           "ipm_launch_times", "ipm_class_stats"]
 
 _lib = None
 
@@ -100,6 +119,8 @@ def load(path=None):
     lib.ipm_set_problem.argtypes = [vp, P(Problem), ip]
     lib.ipm_step.argtypes = [vp, C.c_int, ip, C.c_int, P(StepInfo)]
     lib.ipm_step_static.argtypes = [vp, C.c_int, ip, C.c_int, P(StepInfo)]
+    lib.ipm_launch_times.argtypes = [vp, P(LaunchTime), C.c_int, ip]
+    lib.ipm_class_stats.argtypes = [vp, C.c_int, P(ClassStat), C.c_int, ip]
     lib.ipm_query.argtypes = [vp, C.c_int, P(StepInfo)]
     lib.ipm_moments.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
     lib.ipm_dual.argtypes = [vp, C.c_int, vp, C.c_size_t, C.c_int]
@@ -363,6 +384,20 @@ class Context:
         n = C.c_int()
         self._check(self.lib.ipm_autotune(self.h, len(ids), arr, int(steps_per_candidate), C.byref(n)))
         return n.value
+
+    def launch_times(self):
+        """Per Newton kernel shape: launches and device ms of the last timing window."""
+        n = C.c_int()
+        buf = (LaunchTime * 64)()
+        self._check(self.lib.ipm_launch_times(self.h, buf, 64, C.byref(n)))
+        return [buf[k].as_dict() for k in range(min(n.value, 64))]
+
+    def class_stats(self, pid):
+        """Cumulative Newton counters per size class of a problem."""
+        n = C.c_int()
+        buf = (ClassStat * 16)()
+        self._check(self.lib.ipm_class_stats(self.h, pid, buf, 16, C.byref(n)))
+        return [buf[k].as_dict() for k in range(min(n.value, 16))]
 
     def timing(self, enable):
         d, u, n = C.c_double(), C.c_double(), C.c_longlong()

@@ -83,15 +83,21 @@ __host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) 
          static_cast<size_t>(slot) * kSlotStride;
 }
 
+// Counters per Newton block (cumulative over steps).
+constexpr int kBlkStats = 4;
+
 struct DualParams {
   const double* __restrict__ phi;   // [Q][kp] Phi, zero padded to kp columns
   const double* __restrict__ wphi;  // [Q][kp] w_q Phi (column 0 holds w_q)
   int N, Q, kp, cells;
+  int kl;                           // Phi columns staged in LDS for this launch's class (<= kp)
   const int8_t* __restrict__ cellN; // modes per cell, or null (all N)
   const double* __restrict__ uhat;  // [cells][M][N]
   double* __restrict__ lam;         // [cells][M][N], in/out
   double* __restrict__ nodal;       // [cells][Q][M], out
-  unsigned long long* __restrict__ blk_stats;  // [gridDim.x][2]: iterations, max
+  // [gridDim.x][kBlkStats]: Newton iterations, their max over the block's
+  // cells, cells the block solved (listed), iterations with a fresh Hessian
+  unsigned long long* __restrict__ blk_stats;
   ClosureParams cp;
   double tau;
   int max_newton, one_shot;
@@ -257,7 +263,7 @@ __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lam
     double L[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) L[a] = 0.0;
-    const double* ph = phiL + q * P.kp;
+    const double* ph = phiL + q * P.kl;
 #pragma unroll 4
     for (int i = 0; i < Nc; ++i) {
       const double f = ph[i];
@@ -372,7 +378,9 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   if (!__syncthreads_or(cell >= 0)) return;
 
-  const int Q = P.Q, kp = P.kp, N = P.N;
+  // kp: LDS stride of the staged table (the class's columns), kg: the
+  // global table's
+  const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
   // the cell's dual and moments are requested before the tables are staged,
   // so the two memory round trips overlap; unknown (i, a) of row
   // ro = i * M + a; rows r + s * G of this lane
@@ -396,8 +404,9 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   double* phiL = smem;
   double* wphiL = phiL + Q * kp;
   for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) {
-    phiL[k] = P.phi[k];
-    wphiL[k] = P.wphi[k];
+    const int g = (k / kp) * kg + k % kp;
+    phiL[k] = P.phi[g];
+    wphiL[k] = P.wphi[g];
   }
   const const_dptr phiC = (const_dptr)(P.phi);
   const int gidx_l = wave * CPW + grp;
@@ -417,7 +426,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
       __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max(static_cast<double>(nc))));
   (void)kmax;
 
-  int its = 0;
+  int its = 0, nfresh = 0;
   unsigned status = 0;
   double sx = 0.0, sy = 0.0;
   if (cell >= 0) {
@@ -521,7 +530,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 #pragma unroll
               for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
             }
-            const_dptr ph = phiC + q * kp;  // uniform: scalar loads
+            const_dptr ph = phiC + q * kg;  // uniform: scalar loads
 #pragma unroll
             for (int c = 0; c < NP; ++c) {
               const double v = ph[c / M];
@@ -800,6 +809,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 #pragma unroll
       for (int s = 0; s < R; ++s) lam[s] = lt[s];
       ++its;
+      nfresh += fresh ? 1 : 0;
       if (!ok) {
         status |= kStRealizability;
         break;
@@ -838,7 +848,10 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   sx = wave_max(sx);
   sy = wave_max(sy);
   if (r == 0) {
-    stats[(wave * CPW + grp) * 2 + 0] = static_cast<double>(its);
+    // iterations, fresh ones and the listed flag packed exactly in one double
+    // (its <= max_newton < 1024)
+    stats[(wave * CPW + grp) * 2 + 0] =
+        static_cast<double>(its + 1024 * nfresh + (cell >= 0 ? 1048576 : 0));
     stats[(wave * CPW + grp) * 2 + 1] = static_cast<double>(status);
   }
   if (lane == 0) {
@@ -847,13 +860,16 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long sum_its = 0, max_its = 0;
+    unsigned long long sum_its = 0, max_its = 0, listed = 0, sum_fresh = 0;
     unsigned st = 0;
     double mx = 0.0, my = 0.0;
     for (int k = 0; k < waves * CPW; ++k) {
-      const unsigned long long it = static_cast<unsigned long long>(stats[2 * k]);
+      const unsigned long long v = static_cast<unsigned long long>(stats[2 * k]);
+      const unsigned long long it = v & 1023ull;
       sum_its += it;
       max_its = it > max_its ? it : max_its;
+      sum_fresh += (v >> 10) & 1023ull;
+      listed += v >> 20;
       st |= static_cast<unsigned>(stats[2 * k + 1]);
     }
     for (int w = 0; w < waves; ++w) {
@@ -862,9 +878,11 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
     }
     const int slot = (blk & (kSlots - 1)) * kSlotStride;
     if (P.mode == 0) {
-      unsigned long long* bs = P.blk_stats + 2 * blk;
+      unsigned long long* bs = P.blk_stats + kBlkStats * static_cast<size_t>(blk);
       bs[0] += sum_its;
       if (max_its > bs[1]) bs[1] = max_its;
+      bs[2] += listed;
+      bs[3] += sum_fresh;
       if (st) atomicOr(&P.ctrl->status, st);
       atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
       if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));

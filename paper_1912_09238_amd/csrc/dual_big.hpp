@@ -110,7 +110,9 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   if (cell < 0) return;  // uniform over the workgroup
 
-  const int Q = P.Q, kp = P.kp, N = P.N;
+  // kp: LDS stride of the staged table (the class's columns), kg: the
+  // global table's
+  const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
   const int tid = threadIdx.x;
   extern __shared__ double smem[];
   double* phiL = smem;
@@ -121,8 +123,8 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   double* col = JS + Q * NJ;       // [2][NPB]
   double* xk = col + 2 * NPB;      // [2]
   double* red = xk + 2;            // [32]
-  for (int k = tid; k < Q * kp; k += 256) phiL[k] = P.phi[k];
-  for (int q = tid; q < Q; q += 256) wL[q] = P.wphi[static_cast<size_t>(q) * kp];
+  for (int k = tid; k < Q * kp; k += 256) phiL[k] = P.phi[(k / kp) * kg + k % kp];
+  for (int q = tid; q < Q; q += 256) wL[q] = P.wphi[static_cast<size_t>(q) * kg];
   // precision form: FP32 Hessian blocks and the constant B fragments phi_k(q)
   const int NT = Cfg::block_tiles(kp), QC = (Q + 31) / 32, S16 = 16 * NT;
   float* Hb = reinterpret_cast<float*>(red + 32);                        // [NJ][S16][S16]
@@ -134,7 +136,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int q = c * 32 + 8 * (lane >> 4) + j;
-      const float v = (q < Q && k < N) ? static_cast<float>(phiL[q * kp + k]) : 0.0f;
+      const float v = (q < Q && k < N && k < kp) ? static_cast<float>(phiL[q * kp + k]) : 0.0f;
       __bf16 h, l;
       split_bf16(v, h, l);
       hi[j] = h;
@@ -168,7 +170,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   const int tr = tid >> 4, tc = tid & 15;
   const int jidx = Packed<M>::idx(tr % M, tc % M);
 
-  int its = 0;
+  int its = 0, nfresh = 0;
   unsigned status = 0;
   double ssum = 0.0;
   int ok = eval_nodes<M>(P, lamS, Nc, phiL, wL, 1, tid, 256, US, JS, ssum);
@@ -502,6 +504,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     }
     lam = lt;
     ++its;
+    nfresh += stale ? 0 : 1;
     if (!ok) {
       status |= kStRealizability;
       break;
@@ -545,9 +548,11 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     const double my = nan_max(nan_max(red[1], red[3]), nan_max(red[5], red[7]));
     const int slot = (blk & (kSlots - 1)) * kSlotStride;
     if (P.mode == 0) {
-      unsigned long long* bs = P.blk_stats + 2 * blk;
+      unsigned long long* bs = P.blk_stats + kBlkStats * static_cast<size_t>(blk);
       bs[0] += static_cast<unsigned long long>(its);
       if (static_cast<unsigned long long>(its) > bs[1]) bs[1] = static_cast<unsigned long long>(its);
+      bs[2] += 1ull;
+      bs[3] += static_cast<unsigned long long>(nfresh);
       if (status) atomicOr(&P.ctrl->status, status);
       atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
       if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));

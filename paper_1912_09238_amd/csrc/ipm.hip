@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -48,6 +49,7 @@ struct DualClass {
   int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
   bool merged = false;      // its cells go to the lists of a larger class
   double* d_hinv = nullptr; // inexact-Hessian Newton: stored inverses of the class's cells
+  int n_min = 0, n_max = 0; // unknowns of the cells its launches solve (set-up)
 };
 
 // Problems up to this many cells are latency bound: one Newton launch for
@@ -126,6 +128,7 @@ struct BatchLaunch {
   int n = 0;        // problems (entries) in the launch
   int pid = -1;     // residual: problem id
   int parity = 0;   // residual: step parity
+  int M = 0, lanes = 0, workgroup = 0, variant = 0;  // Newton: kernel shape (timing records)
 };
 
 // Problems stepped together: both step parities prepared once, as launch
@@ -190,6 +193,15 @@ struct ipm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs: dual start/stop, update start/stop
   size_t ev_used = 0;
+  // per batched Newton launch while timing: its shape key and event pair
+  struct LaunchRec {
+    int M, lanes, workgroup, variant, threads;
+    size_t ev;  // index of the start event in lev
+  };
+  std::vector<LaunchRec> lrec;
+  std::vector<hipEvent_t> lev;
+  size_t lev_used = 0;
+  std::vector<ipm_launch_time> ltimes;  // totals of the last timing window
   unsigned long long gen = 0;              // bumped when problems or launch shapes change
   std::unique_ptr<BatchPlan> batch;        // cached plan of the last batched ipm_step
   std::map<std::string, int> tuned_waves;  // autotuner: wavefronts per Newton block by shape
@@ -233,23 +245,28 @@ DualFn pick_big(int M, int T, int prec = 0) {
   return nullptr;
 }
 
+// LDS of a workgroup-kernel variant (the reuse bit's matrix-vector area is
+// added by plan when the variant has no MFMA block area to hold it)
 size_t big_lds_bytes(int M, int T, int Q, int kp, int prec = 0, bool bcache = true) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
-    if (prec & 1) switch (T) {  // the reuse bit adds its own area (see plan)
-        case 5: return BigCfg<MM, 5, 1>::lds_bytes(Q, kp, bcache);
-        case 6: return BigCfg<MM, 6, 1>::lds_bytes(Q, kp, bcache);
-        case 8: return BigCfg<MM, 8, 1>::lds_bytes(Q, kp, bcache);
-        default: return BigCfg<MM, 9, 1>::lds_bytes(Q, kp, bcache);
+    auto g = [&](auto ptag) -> size_t {
+      constexpr int PR = decltype(ptag)::value;
+      switch (T) {
+        case 1: return BigCfg<MM, 1, PR>::lds_bytes(Q, kp, bcache);
+        case 2: return BigCfg<MM, 2, PR>::lds_bytes(Q, kp, bcache);
+        case 4: return BigCfg<MM, 4, PR>::lds_bytes(Q, kp, bcache);
+        case 5: return BigCfg<MM, 5, PR>::lds_bytes(Q, kp, bcache);
+        case 6: return BigCfg<MM, 6, PR>::lds_bytes(Q, kp, bcache);
+        case 8: return BigCfg<MM, 8, PR>::lds_bytes(Q, kp, bcache);
+        default: return BigCfg<MM, 9, PR>::lds_bytes(Q, kp, bcache);
       }
-    switch (T) {
-      case 1: return BigCfg<MM, 1>::lds_bytes(Q, kp);
-      case 2: return BigCfg<MM, 2>::lds_bytes(Q, kp);
-      case 4: return BigCfg<MM, 4>::lds_bytes(Q, kp);
-      case 5: return BigCfg<MM, 5>::lds_bytes(Q, kp);
-      case 6: return BigCfg<MM, 6>::lds_bytes(Q, kp);
-      case 8: return BigCfg<MM, 8>::lds_bytes(Q, kp);
-      default: return BigCfg<MM, 9>::lds_bytes(Q, kp);
+    };
+    switch (prec & 3) {
+      case 1: return g(std::integral_constant<int, 1>{});
+      case 2: return g(std::integral_constant<int, 2>{});
+      case 3: return g(std::integral_constant<int, 3>{});
+      default: return g(std::integral_constant<int, 0>{});
     }
   };
   if (M == 1) return f(std::integral_constant<int, 1>{});
@@ -346,6 +363,14 @@ void free_problem(Problem* P) {
   }
 }
 
+// Phi columns a class's Newton kernel stages in LDS: those its rows read
+// (the lane groups' padded rows for register rows; 16 T / m for the tiles),
+// at most the global table's
+int class_kl(int M, int kp, int NP, int T) {
+  const int k = T > 0 ? (16 * T + M - 1) / M : dual_table_columns(M, NP);
+  return std::min(kp, k);
+}
+
 // shape key of a small-kernel class for the autotuner
 std::string tune_key(const Problem& P, const DualClass& D) {
   return std::to_string(P.M) + "," + std::to_string(D.NP) + "," + std::to_string(P.Q) + "," +
@@ -411,7 +436,7 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
       // wavefronts per block: the most wavefronts per CU that LDS allows
       // (160 KiB per CU); ties go to the larger block
       auto per_cu = [&](int w) {
-        const size_t b = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, w);
+        const size_t b = dual_lds_bytes(P.M, D.NP, P.Q, class_kl(P.M, P.kp, D.NP, 0), w);
         return b > ctx->max_lds ? 0 : w * static_cast<int>(std::min<size_t>(4, (160 * 1024) / b));
       };
       D.waves = 4;
@@ -419,9 +444,9 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
         if (per_cu(w) > per_cu(D.waves)) D.waves = w;
       auto tw = ctx->tuned_waves.find(tune_key(P, D));
       if (tw != ctx->tuned_waves.end() &&
-          dual_lds_bytes(P.M, D.NP, P.Q, P.kp, tw->second) <= ctx->max_lds)
+          dual_lds_bytes(P.M, D.NP, P.Q, class_kl(P.M, P.kp, D.NP, 0), tw->second) <= ctx->max_lds)
         D.waves = tw->second;
-      D.lds = dual_lds_bytes(P.M, D.NP, P.Q, P.kp, D.waves);
+      D.lds = dual_lds_bytes(P.M, D.NP, P.Q, class_kl(P.M, P.kp, D.NP, 0), D.waves);
       // many nodes: the per-cell node buffers of a wavefront's cells leave
       // fewer than two wavefronts per CU (or do not fit), so the class runs
       // on the workgroup-per-cell kernel
@@ -437,12 +462,13 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
       // the inexact-Hessian areas (17 x 16T doubles) live in the MFMA block
       // area when there is one
       const size_t extra = ((D.prec & 2) && !(D.prec & 1)) ? sizeof(double) * 17 * 16 * D.T : 0;
-      D.lds = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, true) + extra;
+      const int kl = class_kl(P.M, P.kp, D.NP, D.T);
+      D.lds = big_lds_bytes(P.M, D.T, P.Q, kl, D.prec, true) + extra;
       if (D.prec & 1) {
         // build the B fragments on the fly instead of caching them when the
         // cache does not fit, or when it would cost the second workgroup
         // per CU that the registers allow (160 KiB of LDS per CU)
-        const size_t lean = big_lds_bytes(P.M, D.T, P.Q, P.kp, D.prec, false) + extra;
+        const size_t lean = big_lds_bytes(P.M, D.T, P.Q, kl, D.prec, false) + extra;
         const size_t cu = 160 * 1024;
         if (D.lds > ctx->max_lds || (2 * D.lds > cu && 2 * lean <= cu)) {
           D.bcache = 0;
@@ -500,6 +526,7 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   d.N = P.N;
   d.Q = P.Q;
   d.kp = P.kp;
+  d.kl = P.kp;
   d.cells = cells;
   d.cellN = cellN;
   d.uhat = uhat;
@@ -524,6 +551,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
   const DualClass& D = P.cls[c];
   d.cls = c;
   d.bcache = D.bcache;
+  d.kl = class_kl(P.M, P.kp, D.NP, D.T);
   int items;
   if (ghost_cells >= 0) {
     d.list_cap = 0;
@@ -534,13 +562,13 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     d.lists = D.d_lists + static_cast<size_t>(d.parity) * kSlots * D.cap;
     d.list_cap = D.cap;
     items = kSlots * D.cap;
-    d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+    d.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.blk_off);
   } else {
     d.list_cap = 0;
     d.order = D.d_order;
     d.order_len = D.order_len;
     items = D.order_len;
-    d.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+    d.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.blk_off);
   }
   if (items == 0) return IPM_OK;
   // the inverse tiles belong to the problem's cells: the Dirichlet ghosts'
@@ -717,7 +745,8 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
   begins.clear();
   for (int ph = 0; ph < 2; ++ph) {
     std::map<std::string, std::vector<NEntry>> ng;
-    std::map<std::string, std::pair<int, int>> nshape;  // key -> (threads, M)
+    std::map<std::string, std::pair<int, int>> nshape;  // key -> (threads, cells per block)
+    std::map<std::string, std::array<int, 4>> nkind;    // key -> (M, lanes, workgroup, variant)
     std::map<std::string, const void*> nfn;
     std::map<std::string, std::vector<UEntry>> ug;
     std::map<std::string, const void*> ufn;
@@ -735,9 +764,10 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
         DualParams dc = d;
         dc.cls = c;
         dc.bcache = D.bcache;
+        dc.kl = class_kl(P.M, P.kp, D.NP, D.T);
         dc.reset_next = first ? 1 : 0;
         first = false;
-        dc.blk_stats = P.d_blk + 2 * static_cast<size_t>(D.blk_off);
+        dc.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.blk_off);
         if (D.prec & 2) P.set_hinv(dc, D);
         int items;
         if (P.lists()) {
@@ -757,6 +787,7 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
                                 std::to_string(D.prec);
         ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
         nshape[key] = {threads, per_block};
+        nkind[key] = {P.M, D.NP, D.T > 0 ? 1 : 0, D.prec};
         nfn[key] = pick_newton_batched(P.M, D.NP, D.T, D.prec);
         if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
       }
@@ -779,6 +810,10 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
       L.fn = nfn[kv.first];
       L.threads = nshape[kv.first].first;
       L.per_block = nshape[kv.first].second;
+      L.M = nkind[kv.first][0];
+      L.lanes = nkind[kv.first][1];
+      L.workgroup = nkind[kv.first][2];
+      L.variant = nkind[kv.first][3];
       L.lists = kv.second.front().d.list_cap > 0 || kv.second.front().d.lists != nullptr;
       L.pofs = dps.size();
       L.bofs = static_cast<int>(begins.size());
@@ -939,7 +974,20 @@ ipm_status launch_batch_step(ipm_ctx* ctx, const BatchPlan& B, int ph, hipEvent_
         HIPCHK(ctx, hipGetLastError());
       }
       void* args[3] = {&pp, &bg, &n};
+      hipEvent_t* le = nullptr;
+      if (e && L.kind == 0) {
+        while (ctx->lev.size() < ctx->lev_used + 2) {
+          hipEvent_t x;
+          HIPCHK(ctx, hipEventCreate(&x));
+          ctx->lev.push_back(x);
+        }
+        le = &ctx->lev[ctx->lev_used];
+        ctx->lrec.push_back({L.M, L.lanes, L.workgroup, L.variant, L.threads, ctx->lev_used});
+        ctx->lev_used += 2;
+        HIPCHK(ctx, hipEventRecord(le[0], ctx->stream));
+      }
       HIPCHK(ctx, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.threads), args, L.lds, ctx->stream));
+      if (le) HIPCHK(ctx, hipEventRecord(le[1], ctx->stream));
     } else {
       const Problem& P = *get(ctx, L.pid);
       hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(256), 0, ctx->stream, P.d_ctrl, P.d_res,
@@ -1249,6 +1297,7 @@ ipm_status ipm_destroy(ipm_ctx* ctx) {
   }
   for (auto& p : ctx->problems) free_problem(p.get());
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->lev) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return IPM_OK;
@@ -1321,6 +1370,27 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   st = plan(ctx, P, plan_counts);
   if (st != IPM_OK) return st;
   for (int c = 0; c < kCls; ++c) P.cls[c].order_len = counts[c];
+  {
+    // unknowns per launching class (cells of a merged class run in the
+    // larger class's launch): the range over its cells, or over every level
+    // for adaptive problems
+    auto note = [&](int c, int n) {
+      int t = static_cast<int>((P.cls_map >> (4 * c)) & 15u);
+      DualClass& D = P.cls[t];
+      D.n_min = D.n_min == 0 ? n : std::min(D.n_min, n);
+      D.n_max = std::max(D.n_max, n);
+    };
+    if (P.adapt) {
+      for (int dg = P.min_degree; dg <= P.degree; ++dg) {
+        const int n = binom_basis(pb->p, dg) * P.M;
+        note(size_class(n), n);
+      }
+    } else if (!cellN.empty()) {
+      for (int c = 0; c < P.cells; ++c) note(cell_cls[c], cellN[c] * P.M);
+    } else {
+      note(size_class(P.M * P.N), P.M * P.N);
+    }
+  }
 
   const size_t fp = ipm_problem_footprint(pb);
   if (ctx->budget && ctx->used + fp > ctx->budget)
@@ -1369,7 +1439,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   ALLOC(P.d_nodal, nod * sizeof(double));
   ALLOC(P.d_ghost, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double));
   ALLOC(P.d_res, static_cast<size_t>(P.upd_blocks) * sizeof(double));
-  ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long));
+  ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * kBlkStats * sizeof(unsigned long long));
   for (DualClass& D : P.cls) {
     if (D.cap > 0) ALLOC(D.d_lists, 2 * static_cast<size_t>(kSlots) * D.cap * sizeof(int));
     if (P.uneven && D.order_len > 0) ALLOC(D.d_order, static_cast<size_t>(D.order_len) * sizeof(int));
@@ -1490,7 +1560,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     CHK(hipMemcpyAsync(&P.d_ctrl->list_len[0], lens.data(), lens.size() * sizeof(unsigned),
                        hipMemcpyHostToDevice, s));
   }
-  CHK(hipMemsetAsync(P.d_blk, 0, static_cast<size_t>(P.dual_blocks) * 2 * sizeof(unsigned long long), s));
+  CHK(hipMemsetAsync(P.d_blk, 0, static_cast<size_t>(P.dual_blocks) * kBlkStats * sizeof(unsigned long long), s));
   CHK(hipMemsetAsync(P.d_res, 0, static_cast<size_t>(P.upd_blocks) * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_ghost, 0, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_nodal, 0, nod * sizeof(double), s));
@@ -2008,7 +2078,7 @@ ipm_status ipm_autotune(ipm_ctx* ctx, int n_ids, const int* ids, int steps_per_c
     const int order[6] = {0, 1, 2, 2, 1, 0};
     for (int o = 0; o < 6 && st == IPM_OK; ++o) {
       const int wi = order[o], w = 1 << wi;
-      const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, P0->kp, w);
+      const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, class_kl(P0->M, P0->kp, D0.NP, 0), w);
       if (lds > ctx->max_lds) continue;
       fits[wi] = true;
       for (auto& pc : kv.second) {
@@ -2044,7 +2114,7 @@ ipm_status ipm_autotune(ipm_ctx* ctx, int n_ids, const int* ids, int steps_per_c
     const int wd = planned == 1 ? 0 : planned == 2 ? 1 : 2;
     if (fits[wd] && total[wd] <= 1.03f * best_ms) best = planned;
     if (st != IPM_OK) break;
-    const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, P0->kp, best);
+    const size_t lds = dual_lds_bytes(P0->M, D0.NP, P0->Q, class_kl(P0->M, P0->kp, D0.NP, 0), best);
     for (auto& pc : kv.second) {
       pc.first->cls[pc.second].waves = best;
       pc.first->cls[pc.second].lds = lds;
@@ -2068,9 +2138,29 @@ ipm_status ipm_kernel_timing(ipm_ctx* ctx, int enable, double* dual_ms, double* 
   if (enable) {
     ctx->timing = true;
     ctx->ev_used = 0;
+    ctx->lev_used = 0;
+    ctx->lrec.clear();
     return IPM_OK;
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->ltimes.clear();
+  for (const auto& r : ctx->lrec) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->lev[r.ev], ctx->lev[r.ev + 1]));
+    ipm_launch_time* t = nullptr;
+    for (auto& x : ctx->ltimes)
+      if (x.m == r.M && x.lanes == r.lanes && x.workgroup == r.workgroup && x.variant == r.variant &&
+          x.threads == r.threads)
+        t = &x;
+    if (!t) {
+      ctx->ltimes.push_back(ipm_launch_time{r.M, r.lanes, r.workgroup, r.variant, r.threads, 0, 0.0});
+      t = &ctx->ltimes.back();
+    }
+    ++t->launches;
+    t->ms += ms;
+  }
+  ctx->lrec.clear();
+  ctx->lev_used = 0;
   double td = 0.0, tu = 0.0;
   for (size_t k = 0; k + 3 < ctx->ev_used; k += 4) {
     float a = 0.f, b = 0.f;
@@ -2084,6 +2174,45 @@ ipm_status ipm_kernel_timing(ipm_ctx* ctx, int enable, double* dual_ms, double* 
   if (launches) *launches = static_cast<long long>(ctx->ev_used / 4);
   ctx->timing = false;
   ctx->ev_used = 0;
+  return IPM_OK;
+}
+
+ipm_status ipm_launch_times(ipm_ctx* ctx, ipm_launch_time* out, int cap, int* n) {
+  if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return fail(ctx, IPM_E_ARG, "ipm_launch_times: bad arguments");
+  *n = static_cast<int>(ctx->ltimes.size());
+  for (int k = 0; k < *n && k < cap; ++k) out[k] = ctx->ltimes[k];
+  return IPM_OK;
+}
+
+ipm_status ipm_class_stats(ipm_ctx* ctx, int id, ipm_class_stat* out, int cap, int* n) {
+  Problem* P = get(ctx, id);
+  if (!P) return fail(ctx, IPM_E_STATE, "ipm_class_stats: unknown problem id");
+  if (!n || cap < 0 || (cap > 0 && !out)) return fail(ctx, IPM_E_ARG, "ipm_class_stats: bad arguments");
+  std::vector<unsigned long long> blk(static_cast<size_t>(P->dual_blocks) * kBlkStats);
+  HIPCHK(ctx, hipMemcpyAsync(blk.data(), P->d_blk, blk.size() * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int k = 0;
+  for (int c = 0; c < kCls; ++c) {
+    const DualClass& D = P->cls[c];
+    if (!D.configured || D.n_max == 0) continue;
+    ipm_class_stat s{};
+    s.size_class = c;
+    s.workgroup = D.T > 0 ? 1 : 0;
+    s.lanes = D.NP;
+    s.variant = D.prec;
+    s.n_min = D.n_min;
+    s.n_max = D.n_max;
+    s.cells = D.count;
+    for (int b = D.blk_off; b < D.blk_off + D.blk_cnt; ++b) {
+      s.iterations += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b)]);
+      s.listed += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b) + 2]);
+      s.fresh += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b) + 3]);
+    }
+    if (k < cap) out[k] = s;
+    ++k;
+  }
+  *n = k;
   return IPM_OK;
 }
 

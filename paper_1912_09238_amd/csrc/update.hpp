@@ -454,8 +454,8 @@ __global__ __launch_bounds__(256) void residual_kernel(StepCtrl* C, const double
   unsigned long long it = 0, mx = 0;
   if (close)
     for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
-      it += blk_stats[2 * k];
-      mx = blk_stats[2 * k + 1] > mx ? blk_stats[2 * k + 1] : mx;
+      it += blk_stats[kBlkStats * k];
+      mx = blk_stats[kBlkStats * k + 1] > mx ? blk_stats[kBlkStats * k + 1] : mx;
     }
   rit[threadIdx.x] = it;
   rmx[threadIdx.x] = mx;
