@@ -1,11 +1,17 @@
 """Throughput benchmark of the IPM hot path on one MI355X.
 
-A step is one IPM time step of the whole workload: for every cell the dual
-Newton solve to tau = 1e-10, the kinetic Rusanov flux at the quadrature
-nodes and the moment update (plus the device-side time step).  Workload:
-1D Euler Sod tube, 8192 cells, Legendre degree 9 (N = 10, 30 dual unknowns
-per cell), 20 Gauss-Legendre nodes, Euler entropy, CFL 0.5, t_end = 0.14,
-FP64 throughout.  Inputs are resident in HBM before timing starts.
+Default line (--form headline): the batching workload -- 64 independent 2D
+Euler problems with three uncertainties (sides 64/128/256, 1.59e6 cells),
+per-cell total degree 1..4 (16..140 dual unknowns per cell), 5^3
+Gauss-Legendre nodes, Euler entropy, Rusanov, CFL 0.5 -- stepped together
+(one launch per Newton kernel shape and one update launch per step).  A step
+is one IPM time step of every problem: for every cell the dual Newton solve
+to tau = 1e-10, the kinetic flux at the nodes and the moment update.  The
+value is the mixed-precision form (Hessian on the matrix cores in split BF16
+with FP32 accumulation, stored FP64 inverse Hessians reused while they
+contract, FP64 gradient, tau test and solve); beside it the plain FP64 form
+and the FP64 form with stored inverses, on the same steps from the same
+states.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
@@ -64,6 +70,26 @@ def cpu_baseline(spec, budget_s):
             "sample": "first %d time steps of the same Sod workload (%d cells), %.1f s" % (
                 steps, spec["nx"], dt),
             "kbar": info["newton_iters"] / max(1, info["cell_updates"])}
+
+
+MIXED = dict(precision="bf16", hessian_reuse=2)
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def class_flops(n, m, Q, listed, iterations, fresh, c_closure=80):
+    """Algorithmic FP64-equivalent flops of a size class's Newton work
+    (symmetric minimum): each solved cell evaluates the ansatz and the
+    gradient once on entry; an iteration with a fresh Hessian adds the
+    assembly, the Cholesky solve and the re-evaluation; an iteration with a
+    stored inverse adds its matrix-vector product and the re-evaluation."""
+    N = n // m
+    f_eval = 2 * m * N * Q + Q * c_closure
+    f_grad = 2 * m * N * Q + m * N
+    f_hess = (m * (m + 1) // 2) * (N * (N + 1) // 2) * Q * 2
+    f_chol = n ** 3 / 3 + 2 * n * n + n
+    f_eg = f_eval + f_grad
+    stale = iterations - fresh
+    return listed * f_eg + fresh * (f_hess + f_chol + f_eg) + stale * (2 * n * n + f_eg)
 
 
 def _gpu_context(**kw):
@@ -202,6 +228,219 @@ def batch_form(args):
         "setup_s": t_setup, "autotuned_shapes": tuned,
         "kbar": newton / max(1, done),
     }
+
+
+def _batch_ids(ctx, specs, nodes, extra):
+    from paper_1912_09238_amd import workloads as W
+    return [ctx.set_problem(dict(spec, **extra), ic_nodal=W.ic_nodal(spec, nodes),
+                            cell_degree=W.cell_degrees(spec)) for spec in specs]
+
+
+def _class_totals(ctx, ids):
+    """Newton counters summed over problems per kernel shape."""
+    tot = {}
+    for pid in ids:
+        for c in ctx.class_stats(pid):
+            key = (c["workgroup"], c["lanes"], c["variant"])
+            t = tot.setdefault(key, {"n_min": c["n_min"], "n_max": c["n_max"], "cells": 0,
+                                     "listed": 0, "iterations": 0, "fresh": 0})
+            t["n_min"] = min(t["n_min"], c["n_min"])
+            t["n_max"] = max(t["n_max"], c["n_max"])
+            for k in ("cells", "listed", "iterations", "fresh"):
+                t[k] += c[k]
+    return tot
+
+
+def _kernel_name(m, key):
+    workgroup, lanes, variant = key
+    if workgroup:
+        return "newton_big_batched<%d,%d,%d>" % (m, lanes // 16, variant)
+    return "newton_batched<%d,%d,%d>" % (m, lanes, variant)
+
+
+def timed_batch(ctx, specs, nodes, extra, warmup, steps, m=4, Q=125):
+    """Set up the batch in one form, run `warmup` untimed steps, then time
+    `steps` steps launched one kernel at a time on the context's stream with
+    a HIP event pair around every Newton launch.  Returns the rate, the
+    per-kernel table (launches, mean device time, algorithmic flops per
+    launch from the per-class Newton counters of the same window) and the
+    E / Var of every problem."""
+    import torch
+    ids = _batch_ids(ctx, specs, nodes, extra)
+    cells = sum(sp["nx"] * sp["ny"] for sp in specs)
+    ctx.step(ids, warmup, wait=True)
+    before = ctx.step(ids, 0, wait=True)
+    c0 = _class_totals(ctx, ids)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    ctx.step(ids, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing(False)
+    lt = ctx.launch_times()
+    after = ctx.step(ids, 0, wait=True)
+    c1 = _class_totals(ctx, ids)
+    assert all(a["status"] == 0 for a in after), after
+    assert all(a["steps"] - b["steps"] == steps for a, b in zip(after, before))
+    newton = sum(a["newton_iters"] - b["newton_iters"] for a, b in zip(after, before))
+    kernels = []
+    for t in lt:
+        key = (t["workgroup"], t["lanes"], t["variant"])
+        c = c1[key]
+        d = {k: c[k] - c0[key][k] for k in ("listed", "iterations", "fresh")}
+        assert c["n_min"] == c["n_max"], ("one size per class", key, c)
+        flops = class_flops(c["n_max"], m, Q, d["listed"], d["iterations"], d["fresh"])
+        avg = t["ms"] / t["launches"] * 1e-3
+        kernels.append({"kernel": _kernel_name(m, key), "unknowns": c["n_max"],
+                        "cells": c["cells"], "launches": t["launches"], "us_avg": avg * 1e6,
+                        "share_of_step": t["ms"] * 1e-3 / elapsed,
+                        "listed_per_launch": d["listed"] / t["launches"],
+                        "iterations_per_listed": d["iterations"] / max(1, d["listed"]),
+                        "fresh_per_listed": d["fresh"] / max(1, d["listed"]),
+                        "flops_per_launch": flops / t["launches"],
+                        "achieved_tflops": flops / t["launches"] / avg / 1e12})
+    kernels.sort(key=lambda k: -k["us_avg"] * k["launches"])
+    ev = []
+    for pid in ids:
+        mo = ctx.moments(pid)
+        ev.append((mo[:, :, 0].copy(), np.sum(mo[:, :, 1:] ** 2, axis=2)))
+    for pid in ids:
+        ctx.release(pid)
+    return {"value": cells * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+            "kbar": newton / (cells * steps), "update_ms_per_step": tm["update_ms"] / steps,
+            "kernels": kernels}, ev
+
+
+def _rel_e_var(ev, ev_ref):
+    out = {}
+    for name, j in (("E", 0), ("Var", 1)):
+        num1 = sum(np.abs(a[j] - b[j]).sum() for a, b in zip(ev, ev_ref))
+        den1 = sum(np.abs(b[j]).sum() for b in ev_ref)
+        num2 = sum(((a[j] - b[j]) ** 2).sum() for a, b in zip(ev, ev_ref))
+        den2 = sum((b[j] ** 2).sum() for b in ev_ref)
+        out[name] = {"l1": float(num1 / den1), "l2": float(np.sqrt(num2 / den2))}
+    return out
+
+
+def cpu_baseline_batch(specs, warmup, steps, budget_s):
+    """The oracle (plain FP64 C, OpenMP over cells) on the host cores over the
+    same step window as the GPU (warmup untimed steps, then `steps` timed
+    steps) on the batch's problems of side 64, in order, until budget_s
+    seconds of timed stepping."""
+    import oracle
+    from paper_1912_09238_amd import workloads as W
+    oracle.build()
+    done_cells, timed, used, newton, cu = 0, 0.0, [], 0, 0
+    for k, spec in enumerate(specs):
+        if spec["nx"] != 64:
+            continue
+        o = oracle.Oracle(spec, ic_fn=lambda nd, s=spec: W.ic_nodal(s, nd),
+                          cell_degree=W.cell_degrees(spec))
+        o.step(warmup)
+        i0 = o.info
+        t0 = time.perf_counter()
+        o.step(steps)
+        timed += time.perf_counter() - t0
+        i1 = o.info
+        assert i1["status"] == 0 and i1["steps"] - i0["steps"] == steps, i1
+        newton += i1["newton_iters"] - i0["newton_iters"]
+        cu += i1["cell_updates"] - i0["cell_updates"]
+        done_cells += o.cells * steps
+        used.append(k)
+        del o
+        if timed >= budget_s:
+            break
+    return {"value": done_cells / timed, "unit": "cell-updates/s",
+            "cores": oracle.load().orc_threads(), "kind": "oracle",
+            "sample": "problems %s of the batch (side 64, 4096 cells each), steps %d..%d "
+                      "(the GPU's timed window), %.1f s, FP64 exact Newton" % (
+                          used, warmup, warmup + steps - 1, timed),
+            "kbar": newton / max(1, cu)}
+
+
+def serving_leg(args):
+    """A short window of the serving workload (Poisson arrivals at 200/s, 60 %
+    Burgers / 40 % Sod, degree 3..9) through the library's serving loop, FP64
+    form: p50 / p99 latency from arrival to moments on the host, offered and
+    served cell-updates/s."""
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context(hbm_budget=int(args.budget_gb * 2 ** 30))
+    reqs = []
+    for spec in W.request_stream(rate=args.rate, duration=args.serve_window):
+        nodes, _ = binding.quadrature(1, spec["quad_per_dim"])
+        reqs.append({"spec": spec, "arrival": spec["arrival"], "ic_nodal": W.ic_nodal(spec, nodes)})
+    res = ctx.serve(reqs, steps_per_round=args.round, max_active=args.max_active, moments=False)
+    ctx.close()
+    assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:3]
+    lat = np.array([r["latency"] for r in res])
+    work = sum(r["steps"] * rq["spec"]["nx"] for r, rq in zip(res, reqs))
+    makespan = max(r["finished"] for r in res)
+    return {"workload": "serve_poisson%d_burgers60_sod40_fp64_%gs" % (int(args.rate),
+                                                                       args.serve_window),
+            "requests": len(reqs), "latency_s": {"p50": float(np.percentile(lat, 50)),
+                                                 "p99": float(np.percentile(lat, 99))},
+            "offered_cell_updates_per_s": work / args.serve_window,
+            "served_cell_updates_per_s": work / makespan, "makespan_s": makespan}
+
+
+def headline_form(args):
+    """The default line: the 64-problem batch in the mixed-precision form
+    (value), the plain FP64 form and the FP64 form with stored inverses, on
+    the same window of steps; roofline of the value form's dominant Newton
+    kernel; the oracle on the host over the same window; a short serving
+    leg."""
+    from paper_1912_09238_amd import binding
+    from paper_1912_09238_amd import workloads as W
+    ctx = _gpu_context()
+    specs = W.batch_problems(count=64)
+    nodes, _ = binding.quadrature(3, 5)
+    cells = sum(sp["nx"] * sp["ny"] for sp in specs)
+    hist = np.zeros(5, dtype=np.int64)
+    for sp in specs:
+        hist += np.bincount(W.cell_degrees(sp), minlength=5)
+    forms = {}
+    evs = {}
+    for name, extra in (("mixed", MIXED), ("fp64", {}), ("fp64_reuse", dict(hessian_reuse=2))):
+        forms[name], evs[name] = timed_batch(ctx, specs, nodes, extra, args.warmup, args.steps)
+        print("headline %s: %.4g cell-updates/s, %.1f ms/step" % (
+            name, forms[name]["value"], forms[name]["ms_per_step"]), file=sys.stderr, flush=True)
+    ctx.close()
+    mixed, fp64, reuse = forms["mixed"], forms["fp64"], forms["fp64_reuse"]
+    dom = mixed["kernels"][0]
+    achieved = dom["achieved_tflops"] * 1e12
+    out = {
+        "metric": METRIC, "value": mixed["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+bf16", "data": "synthetic",
+        "config": {"workload": "batch64_euler2d_p3_deg1to4_q125_mixed_precision",
+                   "problems": len(specs), "cells": cells,
+                   "cells_by_degree": {str(k): int(hist[k]) for k in range(1, 5)},
+                   "form": "BF16-split MFMA Hessian (cells of 65..96 unknowns) + stored FP64 "
+                           "inverse Hessians on every cell; FP64 gradient, tau test, solve",
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                     "kernel": dom["kernel"], "us_avg": dom["us_avg"],
+                     "flops_per_launch": dom["flops_per_launch"],
+                     "unknowns": dom["unknowns"]},
+        "fp64_batch": {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+                       "kbar": fp64["kbar"], "kernels": fp64["kernels"]},
+        "speedup_vs_fp64": mixed["value"] / fp64["value"],
+        "fp64_reuse_batch": {"value": reuse["value"], "ms_per_step": reuse["ms_per_step"],
+                             "speedup_vs_fp64": reuse["value"] / fp64["value"]},
+        "bf16_share": mixed["value"] / reuse["value"],
+        "mixed_rel_vs_fp64": _rel_e_var(evs["mixed"], evs["fp64"]),
+        "kbar": mixed["kbar"], "kernels": mixed["kernels"],
+        "update_ms_per_step": mixed["update_ms_per_step"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_batch(specs, args.warmup, args.steps, args.cpu_seconds)
+    if args.serve_window > 0:
+        out["serving"] = serving_leg(args)
+    return out
 
 
 def precision_form(args):
@@ -601,12 +840,15 @@ def sg_form(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--form", choices=["plain", "batch", "serve", "precision", "adapt", "steady",
-                                       "sg"],
-                    default="plain",
-                    help="plain: the Sod throughput line (default); batch / serve / precision / "
-                         "adapt / steady: the batching, serving, precision, adaptive and "
-                         "steady (one-shot, retardation) forms")
+    ap.add_argument("--form", choices=["headline", "plain", "batch", "serve", "precision",
+                                       "adapt", "steady", "sg"],
+                    default="headline",
+                    help="headline: the 64-problem batch, mixed precision vs FP64 (default); "
+                         "plain: the Sod tube in FP64; batch / serve / precision / adapt / "
+                         "steady / sg: the batching, serving, precision, adaptive, steady "
+                         "(one-shot, retardation) and stochastic-Galerkin studies")
+    ap.add_argument("--serve-window", type=float, default=0.25,
+                    help="headline: seconds of request arrivals in the serving leg (0: none)")
     ap.add_argument("--steady-nx", type=int, default=2048)
     ap.add_argument("--sg-steps", type=int, default=400)
     ap.add_argument("--batch-count", type=int, default=64)
@@ -623,8 +865,10 @@ def main():
     ap.add_argument("--prec-steps", type=int, default=20)
     ap.add_argument("--prec-warmup", type=int, default=2)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (headline 20, plain 5000)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before them (headline 5, plain 20)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--trajectory-steps", type=int, default=0,
@@ -636,6 +880,13 @@ def main():
         print("bench.py runs on one GPU only: there is no multi-GPU path (cells would shard "
               "spatially with a one-cell halo per step)", file=sys.stderr)
         sys.exit(2)
+    if args.form == "headline":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 5 if args.warmup is None else args.warmup
+        print(json.dumps(headline_form(args)), flush=True)
+        return
+    args.steps = 5000 if args.steps is None else args.steps
+    args.warmup = 20 if args.warmup is None else args.warmup
     if args.form == "batch":
         print(json.dumps(batch_form(args)), flush=True)
         return

@@ -261,8 +261,8 @@ ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
    parameter arrays and block offsets live in a fixed device array of
    512 KiB per GPU (defined in the library, held until the process ends),
    not in allocations of the call; ids whose arrays would exceed it (per
-   problem and step parity 232 bytes per Newton size class plus 368 for the
-   update: about 2.6 KB for a problem with four classes, so about 200 such
+   problem and step parity 240 bytes per Newton size class plus 368 for the
+   update: about 2.7 KB for a problem with four classes, so about 190 such
    problems) fail with IPM_E_ARG and a message naming the size.  The problems' own state comes from ipm_set_problem as for
    ipm_step.  Every call on a GPU shares that GPU's array, which keeps the
    last call's contents: the first call for an id list (or after another
