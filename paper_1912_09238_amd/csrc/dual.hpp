@@ -249,13 +249,13 @@ __device__ __forceinline__ double recip1(double x) {
 }
 
 // Ansatz at the nodes q = q0, q0 + step, ... of one cell for the dual lamS
-// (interleaved, first Nc modes).  Writes u and packed J to LDS, adds the
-// lane's share of <s_*> to ssum.  Returns the admissible flag.
+// (interleaved, first Nc modes).  Writes u and packed J to LDS slot q - qoff,
+// adds the lane's share of <s_*> to ssum.  Returns the admissible flag.
 template <int M>
 __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lamS, int Nc,
                                           const double* phiL, const double* wq, int wstride,
                                           int q0, int step, double* US, double* JS,
-                                          double& ssum) {
+                                          double& ssum, int qoff = 0) {
   constexpr int NJ = M * (M + 1) / 2;
   int ok = 1;
 #pragma unroll 1
@@ -273,9 +273,9 @@ __device__ __forceinline__ int eval_nodes(const DualParams& P, const double* lam
     double u[M], J[NJ], ss;
     ok &= closure<M>(P.cp, L, u, J, ss) ? 1 : 0;
 #pragma unroll
-    for (int a = 0; a < M; ++a) US[q * M + a] = u[a];
+    for (int a = 0; a < M; ++a) US[(q - qoff) * M + a] = u[a];
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) JS[q * NJ + k] = J[k];
+    for (int k = 0; k < NJ; ++k) JS[(q - qoff) * NJ + k] = J[k];
     ssum = fma(wq[q * wstride], ss, ssum);
   }
   return ok;
@@ -302,8 +302,11 @@ struct NewtonCfg {
   static constexpr int NJ = M * (M + 1) / 2;
   static constexpr int KCOL = (NP + M - 1) / M;  // table columns the rows read
 
+  // nodes held per group at a time: one per lane (a cell's nodes stream
+  // through in chunks), all of them when there are fewer
+  __host__ __device__ static int chunk(int Q) { return Q < G ? Q : G; }
   __host__ __device__ static int group_doubles(int Q) {
-    return NP + Q * (M + NJ) + (kDpp ? 0 : 2 * NP + 2 + NP);
+    return NP + chunk(Q) * (M + NJ) + (kDpp ? 0 : 2 * NP + 2 + NP);
   }
   __host__ __device__ static size_t lds_bytes(int Q, int kp, int waves) {
     // tables, per-group work areas, then 2 stats per group + 2 speeds per wave
@@ -411,9 +414,11 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   const const_dptr phiC = (const_dptr)(P.phi);
   const int gidx_l = wave * CPW + grp;
   double* lamS = wphiL + Q * kp + static_cast<size_t>(gidx_l) * Cfg::group_doubles(Q);  // [NP]
-  double* US = lamS + NP;         // [Q][M]
-  double* JS = US + Q * M;        // [Q][NJ]
-  double* cA = JS + Q * NJ;       // [2][NP] pivot column (LDS elimination)
+  const int CH = Cfg::chunk(Q);   // nodes per chunk
+  const bool one_chunk = CH == Q; // the chunk holds every node: no re-evaluation
+  double* US = lamS + NP;         // [CH][M]
+  double* JS = US + CH * M;       // [CH][NJ]
+  double* cA = JS + CH * NJ;      // [2][NP] pivot column (LDS elimination)
   double* cX = cA + 2 * NP;       // [2] pivot row's right-hand side
   double* cP = cX + 2;            // [NP] pivots
   double* stats = wphiL + Q * kp + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
@@ -436,8 +441,30 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
     double ssum = 0.0;
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
     auto group_all = [&](int v) -> int { return (__ballot(!v) & gmask) == 0ull ? 1 : 0; };
-    int ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, r, G, US, JS, ssum));
-    wave_sync();
+    // One pass over the nodes for the dual in lamS, chunk by chunk (lane r:
+    // node c0 + r): the ansatz, <s_*> (ssum) and the gradient sums of the
+    // lane's rows, node by node in ascending order.  The last chunk stays
+    // in US / JS.
+    double gacc[R];
+    auto grad_pass = [&]() -> int {
+      int okp = 1;
+      ssum = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) gacc[s] = 0.0;
+      for (int c0 = 0; c0 < Q; c0 += CH) {
+        okp &= eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, c0 + r, Q, US, JS, ssum, c0);
+        wave_sync();
+        const int nq = Q - c0 < CH ? Q - c0 : CH;
+#pragma unroll
+        for (int s = 0; s < R; ++s)
+          if (live[s])
+            for (int j = 0; j < nq; ++j)
+              gacc[s] = fma(US[j * M + aa[s]], wphiL[(c0 + j) * kp + ii[s]], gacc[s]);
+        wave_sync();
+      }
+      return okp;
+    };
+    int ok = group_all(grad_pass());
 
     double g[R];
     auto gradient = [&]() -> double {
@@ -446,10 +473,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
       for (int b = 0; b < M; ++b) e2[b] = 0.0;
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        double gs = 0.0;
-        if (live[s])
-          for (int q = 0; q < Q; ++q) gs = fma(US[q * M + aa[s]], wphiL[q * kp + ii[s]], gs);
-        gs = live[s] ? gs - uh[s] : 0.0;
+        const double gs = live[s] ? gacc[s] - uh[s] : 0.0;
         g[s] = gs;
 #pragma unroll
         for (int b = 0; b < M; ++b) e2[b] += (aa[s] == b) ? gs * gs : 0.0;
@@ -521,22 +545,34 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 #pragma unroll
             for (int b = 0; b < M; ++b) aidx[s][b] = Packed<M>::idx(aa[s], b);
           }
-          for (int q = 0; q < Q; ++q) {
-            const double* Jq = JS + q * NJ;
-            double sb[R][M];
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-              const double wi = wphiL[q * kp + ii[s]] * live_f[s];
-#pragma unroll
-              for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
+          // the nodes in the same ascending order; with several chunks the
+          // ansatz of each chunk is evaluated again for the current dual
+          for (int c0 = 0; c0 < Q; c0 += CH) {
+            if (!one_chunk) {
+              double sdum = 0.0;
+              (void)eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, c0 + r, Q, US, JS, sdum, c0);
+              wave_sync();
             }
-            const_dptr ph = phiC + q * kg;  // uniform: scalar loads
+            const int nq = Q - c0 < CH ? Q - c0 : CH;
+            for (int j = 0; j < nq; ++j) {
+              const int q = c0 + j;
+              const double* Jq = JS + j * NJ;
+              double sb[R][M];
 #pragma unroll
-            for (int c = 0; c < NP; ++c) {
-              const double v = ph[c / M];
+              for (int s = 0; s < R; ++s) {
+                const double wi = wphiL[q * kp + ii[s]] * live_f[s];
 #pragma unroll
-              for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
+                for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
+              }
+              const_dptr ph = phiC + q * kg;  // uniform: scalar loads
+#pragma unroll
+              for (int c = 0; c < NP; ++c) {
+                const double v = ph[c / M];
+#pragma unroll
+                for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
+              }
             }
+            if (!one_chunk) wave_sync();
           }
 #pragma unroll
           for (int s = 0; s < R; ++s)
@@ -783,9 +819,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           lamS[ro[s]] = lt[s];
         }
         wave_sync();
-        ssum = 0.0;
-        ok = group_all(eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, r, G, US, JS, ssum));
-        wave_sync();
+        ok = group_all(grad_pass());
         if (!ls) {
           accepted = 1;
           break;
@@ -831,10 +865,22 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 #pragma unroll
     for (int s = 0; s < R; ++s)
       if (live[s]) P.lam[gidx[s]] = lam[s];
+    // (several chunks: the ansatz of the final dual once more, node by node)
     for (int q = r; q < Q; q += G) {
       double u[M];
+      if (one_chunk) {
 #pragma unroll
-      for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+        for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+      } else {
+        double L[M], J[NJ], ss;
+#pragma unroll
+        for (int a = 0; a < M; ++a) L[a] = 0.0;
+        const double* ph = phiL + q * kp;
+        for (int i = 0; i < Nc; ++i)
+#pragma unroll
+          for (int a = 0; a < M; ++a) L[a] = fma(lamS[i * M + a], ph[i], L[a]);
+        (void)closure<M>(P.cp, L, u, J, ss);
+      }
 #pragma unroll
       for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
       double ax, ay;
