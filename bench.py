@@ -253,6 +253,8 @@ def _class_totals(ctx, ids):
 
 def _kernel_name(m, key):
     workgroup, lanes, variant = key
+    if variant == 10:
+        return "newton_chord_batched<%d,%d>" % (m, lanes)
     if workgroup:
         return "newton_big_batched<%d,%d,%d>" % (m, lanes // 16, variant)
     return "newton_batched<%d,%d,%d>" % (m, lanes, variant)

@@ -1,0 +1,294 @@
+// Chord steps of the inexact-Hessian Newton on the register-row layout.
+//
+// With stored inverse Hessians (the outlook of Sec. 7 on not recomputing the
+// Hessian) almost every Newton iteration (eq:dualIteration1) takes its step
+// from the cell's stored -H^-1: the ansatz and the gradient of eq:L at the
+// nodes, the tau test of eq:tauCrit, one matrix-vector product and the line
+// search of the step length.  None of that needs the Hessian row a lane of
+// the full kernel (dual.hpp) keeps in registers for assembly and inversion,
+// so this kernel runs those iterations alone, with a small register and LDS
+// footprint: many more wavefronts per CU.
+//
+// Per listed cell: while the cell has a valid stored inverse, iterate chord
+// steps exactly as the full kernel does (same arithmetic in the same order:
+// the nodes stream through in chunks, node by node in ascending order; the
+// matrix-vector sum over columns in ascending order).  A cell whose inverse
+// is missing, or whose step fails to contract the dual residual by theta,
+// is marked pending (hinv_ok = 2) with its dual written back; the full
+// kernel, launched next over the same list in pending mode, continues it
+// from there with a fresh Hessian.  Layout: a group of G = NP lanes per
+// cell, lane r holds unknown r = i M + a.
+#pragma once
+
+#include "dual.hpp"
+
+namespace ipm {
+
+template <int M, int NP>
+struct ChordCfg {
+  static constexpr int G = NP;
+  static constexpr int CPW = 64 / G;
+  static constexpr int NJ = M * (M + 1) / 2;
+  // nodes per chunk: one per lane, as the full kernel (the same lanes sum
+  // the same nodes, so both kernels round alike)
+  __host__ __device__ static int chunk(int Q) { return Q < G ? Q : G; }
+  // per group: dual [NP], ansatz [CH][M]
+  __host__ __device__ static int group_doubles(int Q) { return NP + chunk(Q) * M; }
+  // tables Phi [Q][kl] and w [Q], the groups' areas, 2 stats per group and 2
+  // speeds per wavefront
+  __host__ __device__ static size_t lds_bytes(int Q, int kl, int waves) {
+    return sizeof(double) * (static_cast<size_t>(Q) * kl + Q +
+                             static_cast<size_t>(waves) * CPW * group_doubles(Q) +
+                             2 * static_cast<size_t>(waves) * (CPW + 1));
+  }
+};
+
+// Ansatz value u_s(lambda^T phi(xi_q)) of one node (no Jacobian).
+template <int M>
+__device__ __forceinline__ bool node_ansatz(const DualParams& P, const double* lamS, int Nc,
+                                            const double* ph, double (&u)[M], double& ss) {
+  constexpr int NJ = M * (M + 1) / 2;
+  double L[M], J[NJ];
+#pragma unroll
+  for (int a = 0; a < M; ++a) L[a] = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < Nc; ++i) {
+    const double f = ph[i];
+#pragma unroll
+    for (int a = 0; a < M; ++a) L[a] = fma(lamS[i * M + a], f, L[a]);
+  }
+  return closure<M>(P.cp, L, u, J, ss);
+}
+
+template <int M, int NP>
+__device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
+  using Cfg = ChordCfg<M, NP>;
+  constexpr int G = Cfg::G, CPW = Cfg::CPW;
+  const bool stop = P.mode == 0 && ((P.ctrl->done[P.parity] != 0) | (P.ctrl->status != 0u));
+  const int waves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / G;
+  const int r = lane % G;
+  int cell = work_cell(P, (blk * waves + wave) * CPW + grp);
+  if (stop) return;  // uniform
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  // a cell without a valid stored inverse goes to the full kernel at once
+  if (cell >= 0 && P.hinv_ok[cell] != 1) {
+    if (r == 0) P.hinv_ok[cell] = 2;
+    cell = -1;
+  }
+  if (!__syncthreads_or(cell >= 0)) return;
+
+  const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
+  const int Nc = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) : 0;
+  const int nc = Nc * M;
+  const int ii = r / M, aa = r % M;
+  const bool live = r < nc;
+  const size_t gidx = static_cast<size_t>(cell >= 0 ? cell : 0) * M * N + static_cast<size_t>(aa) * N + ii;
+  double lam = live ? P.lam[gidx] : 0.0;
+  const double uh = live ? P.uhat[gidx] : 0.0;
+  extern __shared__ double smem[];
+  double* phiL = smem;         // [Q][kp]
+  double* wL = phiL + Q * kp;  // [Q]
+  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) phiL[k] = P.phi[(k / kp) * kg + k % kp];
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) wL[q] = P.wphi[static_cast<size_t>(q) * kg];
+  const int CH = Cfg::chunk(Q);
+  double* lamS = wL + Q + static_cast<size_t>(wave * CPW + grp) * Cfg::group_doubles(Q);  // [NP]
+  double* US = lamS + NP;                                                                 // [CH][M]
+  double* stats = wL + Q + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
+  __syncthreads();
+
+  int its = 0;
+  unsigned status = 0;
+  bool pending = false;
+  double sx = 0.0, sy = 0.0;
+  if (cell >= 0) {
+    const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
+    auto group_all = [&](int v) -> int { return (__ballot(!v) & gmask) == 0ull ? 1 : 0; };
+    const double* Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
+    lamS[r] = lam;
+    wave_sync();
+    // the nodes in chunks (lane r: node c0 + r): <s_*> and the gradient sum
+    // of this lane's unknown, node by node in ascending order
+    double ssum = 0.0, gacc = 0.0;
+    auto grad_pass = [&]() -> int {
+      int okp = 1;
+      ssum = 0.0;
+      gacc = 0.0;
+      for (int c0 = 0; c0 < Q; c0 += CH) {
+        const int q = c0 + r;
+        if (q < Q) {
+          double u[M], ss;
+          okp &= node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss) ? 1 : 0;
+#pragma unroll
+          for (int a = 0; a < M; ++a) US[r * M + a] = u[a];
+          ssum = fma(wL[q], ss, ssum);
+        }
+        wave_sync();
+        const int nq = Q - c0 < CH ? Q - c0 : CH;
+        if (live)
+          for (int j = 0; j < nq; ++j)
+            gacc = fma(US[j * M + aa], wL[c0 + j] * phiL[(c0 + j) * kp + ii], gacc);
+        wave_sync();
+      }
+      return okp;
+    };
+    double g = 0.0;
+    auto gradient = [&]() -> double {
+      g = live ? gacc - uh : 0.0;
+      double res = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(aa == b ? g * g : 0.0));
+      return res;
+    };
+    int ok = group_all(grad_pass());
+    double res = 0.0;
+    if (ok) res = gradient();
+    else status |= kStRealizability;
+    while (ok) {
+      if (!(res == res) || res > 1e300) {
+        status |= kStNonfinite;
+        break;
+      }
+      if (!P.one_shot) {
+        if (res < P.tau) break;
+        if (its >= P.max_newton) {
+          status |= kStNewton;
+          break;
+        }
+      }
+      // ---- d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area
+      lamS[r] = g;
+      wave_sync();
+      double acc = 0.0;
+      if (live)
+        for (int c = 0; c < nc; ++c) acc = fma(Hc[c * NP + r], lamS[c], acc);
+      const double d = live ? -acc : 0.0;
+      wave_sync();
+      // ---- step length (as the full kernel: backtracking while far from tau)
+      const bool ls = !P.one_shot && res > 1e-6;
+      double L0 = 0.0, slope = 0.0;
+      if (ls) {
+        L0 = group_sum<G>(ssum - lam * uh);
+        slope = group_sum<G>(g * d);
+      }
+      double t = 1.0, lt = lam;
+      int accepted = 0;
+#pragma unroll 1
+      for (int h = 0; h <= 60; ++h) {
+        lt = lam - t * d;
+        lamS[r] = lt;
+        wave_sync();
+        ok = group_all(grad_pass());
+        if (!ls) {
+          accepted = 1;
+          break;
+        }
+        if (ok) {
+          const double Lt = group_sum<G>(ssum - lt * uh);
+          if (Lt <= L0 - 1e-4 * t * slope) {
+            accepted = 1;
+            break;
+          }
+        }
+        t *= 0.5;
+      }
+      if (!accepted) {
+        status |= kStLineSearch;
+        break;
+      }
+      lam = lt;
+      ++its;
+      if (!ok) {
+        status |= kStRealizability;
+        break;
+      }
+      const double res_old = res;
+      res = gradient();
+      // no contraction by theta: the inverse is retired; the cell goes on in
+      // the full kernel (its next iteration assembles afresh), or, one-shot,
+      // at its next pseudo-time step
+      if (!(res <= P.reuse_theta * res_old)) {
+        if (P.one_shot) {
+          if (r == 0) P.hinv_ok[cell] = 0;
+        } else {
+          pending = true;
+        }
+        break;
+      }
+      if (P.one_shot) break;
+    }
+    // ---- write back: the dual; unless pending, the nodal ansatz of the
+    // final dual (once more, node by node) and the wave speeds
+    if (live) P.lam[gidx] = lam;
+    if (pending || status) {
+      if (r == 0 && pending) P.hinv_ok[cell] = 2;
+    } else {
+      for (int q = r; q < Q; q += G) {
+        double u[M], ss;
+        (void)node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss);
+#pragma unroll
+        for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
+        double ax, ay;
+        wave_speeds<M>(P.cp.gamma, P.dim, u, ax, ay);
+        sx = nan_max(sx, ax);
+        sy = nan_max(sy, ay);
+      }
+    }
+  }
+
+  // ---- per-block statistics and speed slots (as the full kernel)
+  sx = wave_max(sx);
+  sy = wave_max(sy);
+  if (r == 0) {
+    stats[(wave * CPW + grp) * 2 + 0] = static_cast<double>(its + (cell >= 0 ? 1048576 : 0));
+    stats[(wave * CPW + grp) * 2 + 1] = static_cast<double>(status);
+  }
+  if (lane == 0) {
+    stats[2 * waves * CPW + 2 * wave] = sx;
+    stats[2 * waves * CPW + 2 * wave + 1] = sy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long sum_its = 0, max_its = 0, listed = 0;
+    unsigned st = 0;
+    double mx = 0.0, my = 0.0;
+    for (int k = 0; k < waves * CPW; ++k) {
+      const unsigned long long v = static_cast<unsigned long long>(stats[2 * k]);
+      const unsigned long long it = v & 1023ull;
+      sum_its += it;
+      max_its = it > max_its ? it : max_its;
+      listed += v >> 20;
+      st |= static_cast<unsigned>(stats[2 * k + 1]);
+    }
+    for (int w = 0; w < waves; ++w) {
+      mx = nan_max(mx, stats[2 * waves * CPW + 2 * w]);
+      my = nan_max(my, stats[2 * waves * CPW + 2 * w + 1]);
+    }
+    const int slot = (blk & (kSlots - 1)) * kSlotStride;
+    unsigned long long* bs = P.blk_stats + kBlkStats * static_cast<size_t>(blk);
+    bs[0] += sum_its;
+    if (max_its > bs[1]) bs[1] = max_its;
+    bs[2] += listed;
+    if (st) atomicOr(&P.ctrl->status, st);
+    atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
+    if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));
+  }
+}
+
+// four wavefronts per SIMD (128 registers)
+template <int M, int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void newton_chord_kernel(DualParams P) {
+  chord_body<M, NP>(P, blockIdx.x);
+}
+
+template <int M, int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void newton_chord_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
+  const int k = batch_problem(begin, n, blockIdx.x);
+  chord_body<M, NP>(PP[k], blockIdx.x - begin[k]);
+}
+
+}  // namespace ipm

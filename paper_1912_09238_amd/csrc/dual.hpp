@@ -91,6 +91,7 @@ struct DualParams {
   const double* __restrict__ wphi;  // [Q][kp] w_q Phi (column 0 holds w_q)
   int N, Q, kp, cells;
   int kl;                           // Phi columns staged in LDS for this launch's class (<= kp)
+  int pend;                         // full kernel after the chord kernel: pending cells only
   const int8_t* __restrict__ cellN; // modes per cell, or null (all N)
   const double* __restrict__ uhat;  // [cells][M][N]
   double* __restrict__ lam;         // [cells][M][N], in/out
@@ -375,10 +376,12 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   const int lane = threadIdx.x & 63;
   const int grp = lane / G;
   const int r = lane % G;
-  const int cell = work_cell(P, (blk * waves + wave) * CPW + grp);
+  int cell = work_cell(P, (blk * waves + wave) * CPW + grp);
   if (stop) return;  // uniform
   // the flux update of this step fills the next step's speed slots and lists
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  // pending mode: only the cells the chord kernel handed on (chord.hpp)
+  if (P.pend && cell >= 0 && P.hinv_ok[cell] != 2) cell = -1;
   if (!__syncthreads_or(cell >= 0)) return;
 
   // kp: LDS stride of the staged table (the class's columns), kg: the
@@ -496,7 +499,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
     // the cell's stored inverse is valid: read once, then kept in step with
     // the flag this cell writes (no re-read of its own write)
     bool have_inv = false;
-    if constexpr (reuse) have_inv = P.hinv_ok[cell] != 0;
+    if constexpr (reuse) have_inv = P.hinv_ok[cell] == 1;  // 2: handed on without one
     double* Hc = nullptr;  // the cell's stored rows of -H^-1, [NP][NP] by column
     if constexpr (reuse)
       Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;

@@ -212,7 +212,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   // the cell's stored inverse is valid: read once, then kept in step with
   // the flag this cell writes (no re-read of its own write)
   bool have_inv = false;
-  if constexpr ((PREC & 2) != 0) have_inv = P.hinv_ok[cell] != 0;
+  if constexpr ((PREC & 2) != 0) have_inv = P.hinv_ok[cell] == 1;
   // d (unknown tid) = sum_c Hinv[tid][c] g[c] from the register tiles, the
   // column sums taken in a fixed order
   auto inverse_times = [&](const double (&A)[T][T], double gv) -> double {

@@ -22,6 +22,7 @@
 #include "ipm.h"
 // this unit defines the non-template kernels it launches itself
 #define IPM_HOST_UNIT
+#include "chord.hpp"
 #include "dual_big.hpp"
 #include "kernel_select.hpp"
 #include "tables.hpp"
@@ -50,6 +51,12 @@ struct DualClass {
   bool merged = false;      // its cells go to the lists of a larger class
   double* d_hinv = nullptr; // inexact-Hessian Newton: stored inverses of the class's cells
   int n_min = 0, n_max = 0; // unknowns of the cells its launches solve (set-up)
+  // register-row inexact-Hessian classes: chord steps in a kernel of their
+  // own, then the full kernel over the cells it handed on
+  bool chord = false;
+  int chord_waves = 4;
+  size_t chord_lds = 0;
+  int cblk_off = 0, cblk_cnt = 0;  // the chord kernel's block statistics
 };
 
 // Problems up to this many cells are latency bound: one Newton launch for
@@ -129,6 +136,7 @@ struct BatchLaunch {
   int pid = -1;     // residual: problem id
   int parity = 0;   // residual: step parity
   int M = 0, lanes = 0, workgroup = 0, variant = 0;  // Newton: kernel shape (timing records)
+  int stage = 1;  // Newton: 0 chord kernels, 1 the others (after stage 0)
 };
 
 // Problems stepped together: both step parities prepared once, as launch
@@ -297,6 +305,21 @@ template <int M, int NP>
 using NC = NewtonCfg<M, NP>;
 
 // dynamic LDS bytes of the Newton kernel
+size_t chord_lds_bytes(int M, int NP, int Q, int kl, int waves) {
+  auto f = [&](auto tag) -> size_t {
+    constexpr int MM = decltype(tag)::value;
+    switch (NP) {
+      case 8: return ChordCfg<MM, 8>::lds_bytes(Q, kl, waves);
+      case 16: return ChordCfg<MM, 16>::lds_bytes(Q, kl, waves);
+      case 32: return ChordCfg<MM, 32>::lds_bytes(Q, kl, waves);
+      default: return ChordCfg<MM, 64>::lds_bytes(Q, kl, waves);
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  if (M == 3) return f(std::integral_constant<int, 3>{});
+  return f(std::integral_constant<int, 4>{});
+}
+
 size_t dual_lds_bytes(int M, int NP, int Q, int kp, int waves) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
@@ -511,6 +534,24 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     D.blk_off = P.dual_blocks;
     D.blk_cnt = (items + per_block - 1) / per_block;
     P.dual_blocks += D.blk_cnt;
+    // chord steps of register-row inexact-Hessian classes in their own
+    // kernel (fixed degrees: adaptive cells change class between steps)
+    D.chord = D.T == 0 && (D.prec & 2) && !P.adapt && D.count > 0 && !D.merged;
+    if (D.chord) {
+      const int kl = class_kl(P.M, P.kp, D.NP, 0);
+      D.chord_waves = 4;
+      while (D.chord_waves > 1 &&
+             chord_lds_bytes(P.M, D.NP, P.Q, kl, D.chord_waves) > ctx->max_lds)
+        D.chord_waves >>= 1;
+      D.chord_lds = chord_lds_bytes(P.M, D.NP, P.Q, kl, D.chord_waves);
+      if (D.chord_lds > ctx->max_lds) {
+        D.chord = false;
+      } else {
+        D.cblk_off = P.dual_blocks;
+        D.cblk_cnt = D.blk_cnt;
+        P.dual_blocks += D.cblk_cnt;
+      }
+    }
   }
   P.dual_blocks = std::max(P.dual_blocks, 1);
   return IPM_OK;
@@ -575,6 +616,20 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
   // set-up runs the exact-Newton variant
   const int prec = ghost_cells >= 0 ? (D.prec & 1) : D.prec;
   if (prec & 2) P.set_hinv(d, D);
+  if (D.chord && ghost_cells < 0 && d.mode == 0) {
+    // chord steps first (own block statistics), then the full kernel over
+    // the cells they handed on
+    DualParams dc = d;
+    dc.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
+    DualFn cf = pick_dual(P.M, D.NP, 10);
+    if (!cf) return fail(ctx, IPM_E_ARG, "no chord kernel for this size");
+    const int cpb = D.chord_waves * dual_cells_per_wave(P.M, D.NP);
+    hipLaunchKernelGGL(cf, dim3((items + cpb - 1) / cpb), dim3(64 * D.chord_waves), D.chord_lds,
+                       ctx->stream, dc);
+    HIPCHK(ctx, hipGetLastError());
+    d.pend = 1;
+    d.reset_next = 0;
+  }
   if (D.T > 0) {
     DualFn fn = pick_big(P.M, D.T, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
@@ -780,9 +835,25 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
           dc.order_len = D.order_len;
           items = D.order_len;
         }
+        if (D.chord) {
+          // stage 0: the chord kernel (own statistics); stage 1: the full
+          // kernel over the cells it hands on
+          DualParams dk = dc;
+          dk.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
+          const int cpb = D.chord_waves * dual_cells_per_wave(P.M, D.NP);
+          const std::string ck = "0:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
+                                 std::to_string(64 * D.chord_waves);
+          ng[ck].push_back({dk, (items + cpb - 1) / cpb, D.chord_lds});
+          nshape[ck] = {64 * D.chord_waves, cpb};
+          nkind[ck] = {P.M, D.NP, 0, 10};
+          nfn[ck] = pick_newton_batched(P.M, D.NP, 0, 10);
+          if (!nfn[ck]) return fail(ctx, IPM_E_ARG, "no batched chord kernel for this size");
+          dc.pend = 1;
+          dc.reset_next = 0;
+        }
         const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
-        const std::string key = std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
+        const std::string key = "1:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                 std::to_string(D.T) + ":" + std::to_string(threads) + ":" +
                                 std::to_string(D.prec);
         ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
@@ -804,9 +875,10 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
         resid.push_back(L);
       }
     }
-    for (auto& kv : ng) {
+    for (auto& kv : ng) {  // keys "0:..." (chord stage) sort before "1:..."
       BatchLaunch L;
       L.kind = 0;
+      L.stage = kv.first[0] == '0' ? 0 : 1;
       L.fn = nfn[kv.first];
       L.threads = nshape[kv.first].first;
       L.per_block = nshape[kv.first].second;
@@ -880,7 +952,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
   // then the steady residuals
   for (int ph = 0; ph < 2; ++ph) {
     HIPCHK(ctx, hipGraphCreate(&B->graph[ph], 0));
-    std::vector<hipGraphNode_t> newton, update;
+    std::vector<hipGraphNode_t> newton, update, chords;
     for (const BatchLaunch& L : B->launches[ph]) {
       hipKernelNodeParams kp{};
       kp.gridDim = dim3(L.blocks);
@@ -895,6 +967,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         int n = L.n;
         std::vector<hipGraphNode_t> deps;
         if (L.kind == 1) deps = newton;
+        if (L.kind == 0 && L.stage == 1) deps = chords;
         if (L.kind == 0 && L.lists) {
           hipKernelNodeParams pk{};
           const DualParams* pdp = B->d_dp + L.pofs;
@@ -916,6 +989,7 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
         kp.kernelParams = args;
         HIPCHK(ctx, hipGraphAddKernelNode(&node, B->graph[ph], deps.data(), deps.size(), &kp));
         (L.kind == 0 ? newton : update).push_back(node);
+        if (L.kind == 0 && L.stage == 0) chords.push_back(node);
       } else {
         const Problem& P = *get(ctx, L.pid);
         StepCtrl* C = P.d_ctrl;
@@ -1031,7 +1105,7 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   // raise the dynamic LDS limit above the 64 KiB default (best effort)
   for (int M : {1, 3, 4})
     for (int NP : {8, 16, 32, 64})
-      for (int prec : {0, 2}) {
+      for (int prec : {0, 2, 10}) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_dual(M, NP, prec)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, big);
         (void)hipFuncSetAttribute(pick_newton_batched(M, NP, 0, prec),
@@ -2211,6 +2285,17 @@ ipm_status ipm_class_stats(ipm_ctx* ctx, int id, ipm_class_stat* out, int cap, i
     }
     if (k < cap) out[k] = s;
     ++k;
+    if (D.chord) {  // the chord kernel's counters (variant 10)
+      ipm_class_stat t = s;
+      t.variant = 10;
+      t.listed = t.iterations = t.fresh = 0;
+      for (int b = D.cblk_off; b < D.cblk_off + D.cblk_cnt; ++b) {
+        t.iterations += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b)]);
+        t.listed += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b) + 2]);
+      }
+      if (k < cap) out[k] = t;
+      ++k;
+    }
   }
   *n = k;
   return IPM_OK;

@@ -15,7 +15,8 @@ using UpdFn = void (*)(UpdateParams);
 using SetupFn = void (*)(SetupParams);
 
 // register-row Newton kernel of NP lanes per cell (prec 0: exact; 2:
-// inexact-Hessian), single problem and batched; null when not built
+// inexact-Hessian; 10: the inexact-Hessian chord steps alone), single
+// problem and batched; null when not built
 template <int M> DualFn dual_pick(int NP, int prec);
 template <int M> const void* dual_batched_pick(int NP, int prec);
 // workgroup-per-cell Newton kernel with T x T tiles (prec bit 0: BF16 MFMA

@@ -2,12 +2,21 @@
 // by one unit per M.
 #pragma once
 
+#include "chord.hpp"
 #include "kernel_select.hpp"
 
 namespace ipm {
 
+// prec 0: exact Newton; 2: inexact-Hessian (full kernel); 10: its chord
+// steps alone (chord.hpp)
 template <int M>
 DualFn dual_pick(int NP, int prec) {
+  if (prec == 10) switch (NP) {
+      case 8: return newton_chord_kernel<M, 8>;
+      case 16: return newton_chord_kernel<M, 16>;
+      case 32: return newton_chord_kernel<M, 32>;
+      case 64: return newton_chord_kernel<M, 64>;
+    }
   if (prec == 2) switch (NP) {
       case 8: return newton_kernel<M, 8, 2>;
       case 16: return newton_kernel<M, 16, 2>;
@@ -26,6 +35,12 @@ DualFn dual_pick(int NP, int prec) {
 
 template <int M>
 const void* dual_batched_pick(int NP, int prec) {
+  if (prec == 10) switch (NP) {
+      case 8: return reinterpret_cast<const void*>(newton_chord_batched<M, 8>);
+      case 16: return reinterpret_cast<const void*>(newton_chord_batched<M, 16>);
+      case 32: return reinterpret_cast<const void*>(newton_chord_batched<M, 32>);
+      case 64: return reinterpret_cast<const void*>(newton_chord_batched<M, 64>);
+    }
   if (prec == 2) switch (NP) {
       case 8: return reinterpret_cast<const void*>(newton_batched<M, 8, 2>);
       case 16: return reinterpret_cast<const void*>(newton_batched<M, 16, 2>);
