@@ -1,0 +1,333 @@
+// Chord steps of the inexact-Hessian Newton for cells of the workgroup
+// kernel (dual_big.hpp: more than 64 unknowns, T x T register tiles).
+//
+// As on register rows (chord.hpp), a chord iteration needs the ansatz and the
+// gradient of eq:L at the nodes, the tau test of eq:tauCrit, the product of
+// the stored inverse Hessian with the gradient, and the step-length search;
+// here one wavefront runs one cell.  Its lane l stands for the four threads
+// l, l + 64, l + 128, l + 192 of the workgroup kernel (as node, as row and as
+// tile owner), and every sum is formed as there: per-thread partial sums,
+// each wavefront-sum over the same 64 threads, the four combined as
+// (w0 + w1) + (w2 + w3); the product with the stored tiles per tile row,
+// then over the 16 column threads in ascending order.  The results are
+// those of the workgroup kernel bit for bit.  A cell without a valid
+// inverse, or whose step fails to contract the dual residual by theta, is
+// handed on (hinv_ok = 2) to the workgroup kernel in pending mode.
+#pragma once
+
+#include "chord.hpp"
+#include "dual_big.hpp"
+
+namespace ipm {
+
+template <int M, int T>
+struct ChordBigCfg {
+  static constexpr int NPB = 16 * T;
+  static constexpr int NJ = M * (M + 1) / 2;
+  // per cell: dual [NPB], ansatz [Q][M], gradient [NPB], step [NPB]
+  __host__ __device__ static int cell_doubles(int Q) { return 3 * NPB + Q * M; }
+  // tables Phi [Q][kl] and w [Q], the cells' areas, 2 stats per cell and 2
+  // speeds per wavefront
+  __host__ __device__ static size_t lds_bytes(int Q, int kl, int waves) {
+    return sizeof(double) * (static_cast<size_t>(Q) * kl + Q +
+                             static_cast<size_t>(waves) * (cell_doubles(Q) + 4));
+  }
+};
+
+// sum over the workgroup kernel's 256 threads, thread 64 s + lane in slot s
+__device__ __forceinline__ double wg_sum4(const double (&x)[4]) {
+  return (wave_sum(x[0]) + wave_sum(x[1])) + (wave_sum(x[2]) + wave_sum(x[3]));
+}
+
+template <int M, int T>
+__device__ __forceinline__ void chord_big_body(const DualParams& P, const int blk) {
+  using Cfg = ChordBigCfg<M, T>;
+  constexpr int NPB = Cfg::NPB;
+  const bool stop = P.mode == 0 && ((P.ctrl->done[P.parity] != 0) | (P.ctrl->status != 0u));
+  const int waves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  int cell = work_cell(P, blk * waves + wave);
+  if (stop) return;  // uniform
+  if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  if (cell >= 0 && P.hinv_ok[cell] != 1) {
+    if (lane == 0) P.hinv_ok[cell] = 2;
+    cell = -1;
+  }
+  if (!__syncthreads_or(cell >= 0)) return;
+
+  const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
+  extern __shared__ double smem[];
+  double* phiL = smem;         // [Q][kp]
+  double* wL = phiL + Q * kp;  // [Q]
+  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) phiL[k] = P.phi[(k / kp) * kg + k % kp];
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) wL[q] = P.wphi[static_cast<size_t>(q) * kg];
+  double* lamS = wL + Q + static_cast<size_t>(wave) * (Cfg::cell_doubles(Q) + 4);
+  double* US = lamS + NPB;   // [Q][M]
+  double* gS = US + Q * M;   // [NPB]
+  double* dS = gS + NPB;     // [NPB]
+  double* stats = dS + NPB;  // [4]: its + listed, status, speeds x, y
+  __syncthreads();
+
+  int its = 0;
+  unsigned status = 0;
+  bool pending = false;
+  double sx = 0.0, sy = 0.0;
+  if (cell >= 0) {
+    const int Nc = P.cellN ? static_cast<int>(P.cellN[cell]) : N;
+    const int nc = Nc * M;
+    // the four stand-in threads v = lane + 64 s: unknown v (row), node v
+    bool live[4];
+    int ri[4], ra[4];
+    size_t gidx[4];
+    double lam[4], uh[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int v = lane + 64 * s;
+      live[s] = v < nc;
+      ri[s] = v / M;
+      ra[s] = v % M;
+      gidx[s] = static_cast<size_t>(cell) * M * N + static_cast<size_t>(ra[s]) * N + ri[s];
+      lam[s] = live[s] ? P.lam[gidx[s]] : 0.0;
+      uh[s] = live[s] ? P.uhat[gidx[s]] : 0.0;
+      if (v < NPB) lamS[v] = live[s] ? lam[s] : 0.0;
+    }
+    const double* Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
+    wave_sync();
+    double ssum[4];
+    // the ansatz at node v of each stand-in thread: U to LDS, <s_*> shares
+    auto eval = [&]() -> int {
+      int okp = 1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ssum[s] = 0.0;
+        const int q = lane + 64 * s;
+        if (q < Q) {
+          double u[M], ss;
+          okp &= node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss) ? 1 : 0;
+#pragma unroll
+          for (int a = 0; a < M; ++a) US[q * M + a] = u[a];
+          ssum[s] = fma(wL[q], ss, ssum[s]);
+        }
+      }
+      wave_sync();
+      return __ballot(!okp) == 0ull ? 1 : 0;
+    };
+    double g[4];
+    auto gradient = [&]() -> double {
+      double e2[M][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double gg = 0.0;
+        if (live[s]) {
+          for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra[s]] * wL[q], phiL[q * kp + ri[s]], gg);
+          gg -= uh[s];
+        }
+        g[s] = gg;
+#pragma unroll
+        for (int b = 0; b < M; ++b) e2[b][s] = (live[s] && ra[s] == b) ? gg * gg : 0.0;
+      }
+      double res = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) res += sqrt(wg_sum4(e2[b]));
+      return res;
+    };
+    int ok = eval();
+    double res = 0.0;
+    if (ok) res = gradient();
+    else status |= kStRealizability;
+    while (ok) {
+      if (!(res == res) || res > 1e300) {
+        status |= kStNonfinite;
+        break;
+      }
+      if (!P.one_shot) {
+        if (res < P.tau) break;
+        if (its >= P.max_newton) {
+          status |= kStNewton;
+          break;
+        }
+      }
+      // ---- d = H^-1 g from the stored tiles: tile thread u = 64 s + lane
+      // (rows tr + 16 i, columns tc + 16 j) forms its row sums, the 16
+      // column threads of a row are then added in ascending order
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int v = lane + 64 * s;
+        if (v < NPB) gS[v] = live[s] ? g[s] : 0.0;
+      }
+      wave_sync();
+      const int tc = lane & 15;
+      double gc[T];
+#pragma unroll
+      for (int j = 0; j < T; ++j) gc[j] = gS[tc + 16 * j];
+      // all 256 tile threads (tile rows tr = 0..15 at every T)
+#pragma unroll 1
+      for (int s = 0; s < 4; ++s) {
+        const int u = 64 * s + lane, tr = u >> 4;
+#pragma unroll 1
+        for (int i = 0; i < T; ++i) {
+          double ps = 0.0;
+#pragma unroll
+          for (int j = 0; j < T; ++j) ps = fma(Hc[(i * T + j) * 256 + u], gc[j], ps);
+          double dv = 0.0;
+          dv += row_bcast<0>(ps);
+          dv += row_bcast<1>(ps);
+          dv += row_bcast<2>(ps);
+          dv += row_bcast<3>(ps);
+          dv += row_bcast<4>(ps);
+          dv += row_bcast<5>(ps);
+          dv += row_bcast<6>(ps);
+          dv += row_bcast<7>(ps);
+          dv += row_bcast<8>(ps);
+          dv += row_bcast<9>(ps);
+          dv += row_bcast<10>(ps);
+          dv += row_bcast<11>(ps);
+          dv += row_bcast<12>(ps);
+          dv += row_bcast<13>(ps);
+          dv += row_bcast<14>(ps);
+          dv += row_bcast<15>(ps);
+          if (tc == 0) dS[tr + 16 * i] = dv;
+        }
+      }
+      wave_sync();
+      double d[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int v = lane + 64 * s;
+        d[s] = (live[s] && v < NPB) ? dS[v] : 0.0;
+      }
+      wave_sync();
+      // ---- step length
+      const bool ls = !P.one_shot && res > 1e-6;
+      double L0 = 0.0, slope = 0.0;
+      if (ls) {
+        double x0[4], x1[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          x0[s] = ssum[s] - (live[s] ? lam[s] * uh[s] : 0.0);
+          x1[s] = live[s] ? g[s] * d[s] : 0.0;
+        }
+        L0 = wg_sum4(x0);
+        slope = wg_sum4(x1);
+      }
+      double t = 1.0, lt[4];
+      int accepted = 0;
+#pragma unroll 1
+      for (int h = 0; h <= 60; ++h) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          lt[s] = lam[s] - t * d[s];
+          const int v = lane + 64 * s;
+          if (v < NPB) lamS[v] = live[s] ? lt[s] : 0.0;
+        }
+        wave_sync();
+        ok = eval();
+        if (!ls) {
+          accepted = 1;
+          break;
+        }
+        if (ok) {
+          double x[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) x[s] = ssum[s] - (live[s] ? lt[s] * uh[s] : 0.0);
+          if (wg_sum4(x) <= L0 - 1e-4 * t * slope) {
+            accepted = 1;
+            break;
+          }
+        }
+        t *= 0.5;
+      }
+      if (!accepted) {
+        status |= kStLineSearch;
+        break;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) lam[s] = lt[s];
+      ++its;
+      if (!ok) {
+        status |= kStRealizability;
+        break;
+      }
+      const double res_old = res;
+      res = gradient();
+      if (!(res <= P.reuse_theta * res_old)) {
+        if (P.one_shot) {
+          if (lane == 0) P.hinv_ok[cell] = 0;
+        } else {
+          pending = true;
+        }
+        break;
+      }
+      if (P.one_shot) break;
+    }
+    // ---- write back: the dual; unless handed on, the nodal ansatz and speeds
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (live[s]) P.lam[gidx[s]] = lam[s];
+    if (pending || status) {
+      if (lane == 0 && pending) P.hinv_ok[cell] = 2;
+    } else {
+      for (int q = lane; q < Q; q += 64) {
+        double u[M];
+#pragma unroll
+        for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+#pragma unroll
+        for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
+        double ax, ay;
+        wave_speeds<M>(P.cp.gamma, P.dim, u, ax, ay);
+        sx = nan_max(sx, ax);
+        sy = nan_max(sy, ay);
+      }
+    }
+  }
+
+  // ---- per-block statistics and speed slots
+  sx = wave_max(sx);
+  sy = wave_max(sy);
+  if (lane == 0) {
+    stats[0] = static_cast<double>(its + (cell >= 0 ? 1048576 : 0));
+    stats[1] = static_cast<double>(status);
+    stats[2] = sx;
+    stats[3] = sy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long sum_its = 0, max_its = 0, listed = 0;
+    unsigned st = 0;
+    double mx = 0.0, my = 0.0;
+    for (int w = 0; w < waves; ++w) {
+      const double* o = wL + Q + static_cast<size_t>(w) * (Cfg::cell_doubles(Q) + 4) + Cfg::cell_doubles(Q);
+      const unsigned long long v = static_cast<unsigned long long>(o[0]);
+      const unsigned long long it = v & 1023ull;
+      sum_its += it;
+      max_its = it > max_its ? it : max_its;
+      listed += v >> 20;
+      st |= static_cast<unsigned>(o[1]);
+      mx = nan_max(mx, o[2]);
+      my = nan_max(my, o[3]);
+    }
+    const int slot = (blk & (kSlots - 1)) * kSlotStride;
+    unsigned long long* bs = P.blk_stats + kBlkStats * static_cast<size_t>(blk);
+    bs[0] += sum_its;
+    if (max_its > bs[1]) bs[1] = max_its;
+    bs[2] += listed;
+    if (st) atomicOr(&P.ctrl->status, st);
+    atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
+    if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));
+  }
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void newton_chord_big_kernel(DualParams P) {
+  chord_big_body<M, T>(P, blockIdx.x);
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void newton_chord_big_batched(const DualParams* __restrict__ PP,
+                                                                const int* __restrict__ begin, int n) {
+  const int k = batch_problem(begin, n, blockIdx.x);
+  chord_big_body<M, T>(PP[k], blockIdx.x - begin[k]);
+}
+
+}  // namespace ipm

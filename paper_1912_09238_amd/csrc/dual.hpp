@@ -85,6 +85,9 @@ __host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) 
 
 // Counters per Newton block (cumulative over steps).
 constexpr int kBlkStats = 4;
+// Pending mode (after a chord kernel): few cells remain, so a block walks
+// this many blocks' worth of work items instead of one.
+constexpr int kPendItems = 16;
 
 struct DualParams {
   const double* __restrict__ phi;   // [Q][kp] Phi, zero padded to kp columns
@@ -949,6 +952,13 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 template <int M, int NP, int PREC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
 void newton_kernel(DualParams P) {
+  if (P.pend) {
+    for (int j = 0; j < kPendItems; ++j) {
+      newton_body<M, NP, PREC>(P, blockIdx.x * kPendItems + j);
+      __syncthreads();
+    }
+    return;
+  }
   newton_body<M, NP, PREC>(P, blockIdx.x);
 }
 
@@ -994,6 +1004,13 @@ template <int M, int NP, int PREC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
 void newton_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
+  if (PP[k].pend) {
+    for (int j = 0; j < kPendItems; ++j) {
+      newton_body<M, NP, PREC>(PP[k], (blockIdx.x - begin[k]) * kPendItems + j);
+      __syncthreads();
+    }
+    return;
+  }
   newton_body<M, NP, PREC>(PP[k], blockIdx.x - begin[k]);
 }
 

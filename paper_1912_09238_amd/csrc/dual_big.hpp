@@ -105,9 +105,11 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   constexpr int NPB = Cfg::NPB, NJ = Cfg::NJ;
   // the stop flags are read with the list lengths (one round trip, not two)
   const bool stop = P.mode == 0 && ((P.ctrl->done[P.parity] != 0) | (P.ctrl->status != 0u));
-  const int cell = work_cell(P, blk);
+  int cell = work_cell(P, blk);
   if (stop) return;  // uniform
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
+  // pending mode: only the cells the chord kernel handed on (chord_big.hpp)
+  if (P.pend && cell >= 0 && P.hinv_ok[cell] != 2) cell = -1;
   if (cell < 0) return;  // uniform over the workgroup
 
   // kp: LDS stride of the staged table (the class's columns), kg: the
@@ -572,6 +574,13 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 template <int M, int T, int PREC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
 void newton_big_kernel(DualParams P) {
+  if (P.pend) {  // after the chord kernel: a block walks kPendItems cells
+    for (int j = 0; j < kPendItems; ++j) {
+      newton_big_body<M, T, PREC>(P, blockIdx.x * kPendItems + j);
+      __syncthreads();
+    }
+    return;
+  }
   newton_big_body<M, T, PREC>(P, blockIdx.x);
 }
 
@@ -580,6 +589,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1)
 void newton_big_batched(const DualParams* __restrict__ PP,
                                                           const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
+  if (PP[k].pend) {
+    for (int j = 0; j < kPendItems; ++j) {
+      newton_big_body<M, T, PREC>(PP[k], (blockIdx.x - begin[k]) * kPendItems + j);
+      __syncthreads();
+    }
+    return;
+  }
   newton_big_body<M, T, PREC>(PP[k], blockIdx.x - begin[k]);
 }
 

@@ -23,6 +23,7 @@
 // this unit defines the non-template kernels it launches itself
 #define IPM_HOST_UNIT
 #include "chord.hpp"
+#include "chord_big.hpp"
 #include "dual_big.hpp"
 #include "kernel_select.hpp"
 #include "tables.hpp"
@@ -320,6 +321,23 @@ size_t chord_lds_bytes(int M, int NP, int Q, int kl, int waves) {
   return f(std::integral_constant<int, 4>{});
 }
 
+size_t chord_big_lds_bytes(int M, int T, int Q, int kl, int waves) {
+  auto f = [&](auto tag) -> size_t {
+    constexpr int MM = decltype(tag)::value;
+    switch (T) {
+      case 1: return ChordBigCfg<MM, 1>::lds_bytes(Q, kl, waves);
+      case 2: return ChordBigCfg<MM, 2>::lds_bytes(Q, kl, waves);
+      case 4: return ChordBigCfg<MM, 4>::lds_bytes(Q, kl, waves);
+      case 5: return ChordBigCfg<MM, 5>::lds_bytes(Q, kl, waves);
+      case 6: return ChordBigCfg<MM, 6>::lds_bytes(Q, kl, waves);
+      case 8: return ChordBigCfg<MM, 8>::lds_bytes(Q, kl, waves);
+      default: return ChordBigCfg<MM, 9>::lds_bytes(Q, kl, waves);
+    }
+  };
+  if (M == 1) return f(std::integral_constant<int, 1>{});
+  return f(std::integral_constant<int, 4>{});
+}
+
 size_t dual_lds_bytes(int M, int NP, int Q, int kp, int waves) {
   auto f = [&](auto tag) -> size_t {
     constexpr int MM = decltype(tag)::value;
@@ -536,14 +554,17 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     P.dual_blocks += D.blk_cnt;
     // chord steps of register-row inexact-Hessian classes in their own
     // kernel (fixed degrees: adaptive cells change class between steps)
-    D.chord = D.T == 0 && (D.prec & 2) && !P.adapt && D.count > 0 && !D.merged;
+    // (workgroup classes: one node per stand-in thread, so Q <= 256)
+    D.chord = (D.prec & 2) && !P.adapt && D.count > 0 && !D.merged && (D.T == 0 || P.Q <= 256);
     if (D.chord) {
-      const int kl = class_kl(P.M, P.kp, D.NP, 0);
+      const int kl = class_kl(P.M, P.kp, D.NP, D.T);
+      auto lds_for = [&](int w) {
+        return D.T > 0 ? chord_big_lds_bytes(P.M, D.T, P.Q, kl, w)
+                       : chord_lds_bytes(P.M, D.NP, P.Q, kl, w);
+      };
       D.chord_waves = 4;
-      while (D.chord_waves > 1 &&
-             chord_lds_bytes(P.M, D.NP, P.Q, kl, D.chord_waves) > ctx->max_lds)
-        D.chord_waves >>= 1;
-      D.chord_lds = chord_lds_bytes(P.M, D.NP, P.Q, kl, D.chord_waves);
+      while (D.chord_waves > 1 && lds_for(D.chord_waves) > ctx->max_lds) D.chord_waves >>= 1;
+      D.chord_lds = lds_for(D.chord_waves);
       if (D.chord_lds > ctx->max_lds) {
         D.chord = false;
       } else {
@@ -621,23 +642,24 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     // the cells they handed on
     DualParams dc = d;
     dc.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
-    DualFn cf = pick_dual(P.M, D.NP, 10);
+    DualFn cf = D.T > 0 ? pick_big(P.M, D.T, 10) : pick_dual(P.M, D.NP, 10);
     if (!cf) return fail(ctx, IPM_E_ARG, "no chord kernel for this size");
-    const int cpb = D.chord_waves * dual_cells_per_wave(P.M, D.NP);
+    const int cpb = D.chord_waves * (D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP));
     hipLaunchKernelGGL(cf, dim3((items + cpb - 1) / cpb), dim3(64 * D.chord_waves), D.chord_lds,
                        ctx->stream, dc);
     HIPCHK(ctx, hipGetLastError());
     d.pend = 1;
     d.reset_next = 0;
   }
+  const int pk = d.pend ? kPendItems : 1;  // pending mode: blocks walk several items
   if (D.T > 0) {
     DualFn fn = pick_big(P.M, D.T, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-    hipLaunchKernelGGL(fn, dim3(items), dim3(256), D.lds, ctx->stream, d);
+    hipLaunchKernelGGL(fn, dim3((items + pk - 1) / pk), dim3(256), D.lds, ctx->stream, d);
   } else {
     DualFn fn = pick_dual(P.M, D.NP, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-    const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP);
+    const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP) * pk;
     const int blocks = (items + per_block - 1) / per_block;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * D.waves), D.lds, ctx->stream, d);
   }
@@ -840,22 +862,23 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
           // kernel over the cells it hands on
           DualParams dk = dc;
           dk.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
-          const int cpb = D.chord_waves * dual_cells_per_wave(P.M, D.NP);
+          const int cpb = D.chord_waves * (D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP));
           const std::string ck = "0:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
-                                 std::to_string(64 * D.chord_waves);
+                                 std::to_string(D.T) + ":" + std::to_string(64 * D.chord_waves);
           ng[ck].push_back({dk, (items + cpb - 1) / cpb, D.chord_lds});
           nshape[ck] = {64 * D.chord_waves, cpb};
-          nkind[ck] = {P.M, D.NP, 0, 10};
-          nfn[ck] = pick_newton_batched(P.M, D.NP, 0, 10);
+          nkind[ck] = {P.M, D.NP, D.T > 0 ? 1 : 0, 10};
+          nfn[ck] = pick_newton_batched(P.M, D.NP, D.T, 10);
           if (!nfn[ck]) return fail(ctx, IPM_E_ARG, "no batched chord kernel for this size");
           dc.pend = 1;
           dc.reset_next = 0;
         }
-        const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
+        const int per_block = (D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP)) *
+                              (dc.pend ? kPendItems : 1);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
         const std::string key = "1:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                 std::to_string(D.T) + ":" + std::to_string(threads) + ":" +
-                                std::to_string(D.prec);
+                                std::to_string(D.prec) + (dc.pend ? ":p" : "");
         ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
         nshape[key] = {threads, per_block};
         nkind[key] = {P.M, D.NP, D.T > 0 ? 1 : 0, D.prec};
@@ -1117,8 +1140,8 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, big);
   for (int M : {1, 4})
     for (int T : {1, 2, 4, 5, 6, 8, 9})
-      for (int prec : {0, 1, 2, 3}) {
-        if ((prec & 1) && T < 5) continue;
+      for (int prec : {0, 1, 2, 3, 10}) {
+        if ((prec & 1) && prec != 10 && T < 5) continue;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_big(M, T, prec)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, big);
         (void)hipFuncSetAttribute(pick_newton_batched(M, 16 * T, T, prec),

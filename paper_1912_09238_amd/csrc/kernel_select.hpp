@@ -20,7 +20,8 @@ using SetupFn = void (*)(SetupParams);
 template <int M> DualFn dual_pick(int NP, int prec);
 template <int M> const void* dual_batched_pick(int NP, int prec);
 // workgroup-per-cell Newton kernel with T x T tiles (prec bit 0: BF16 MFMA
-// Hessian, T >= 5; bit 1: inexact-Hessian); M = 1 or 4
+// Hessian, T >= 5; bit 1: inexact-Hessian; 10: its chord steps alone, one
+// cell per wavefront); M = 1 or 4
 template <int M> DualFn big_pick(int T, int prec);
 template <int M> const void* big_batched_pick(int T, int prec);
 // flux update with G lanes per cell, and the set-up kernel

@@ -2,6 +2,7 @@
 // (1 or 4); included by one unit per M.
 #pragma once
 
+#include "chord_big.hpp"
 #include "dual_big.hpp"
 #include "kernel_select.hpp"
 
@@ -27,6 +28,15 @@ DualFn big_prec_pick(int T) {
 
 template <int M>
 DualFn big_pick(int T, int prec) {
+  if (prec == 10) switch (T) {  // the chord steps alone (chord_big.hpp)
+      case 1: return newton_chord_big_kernel<M, 1>;
+      case 2: return newton_chord_big_kernel<M, 2>;
+      case 4: return newton_chord_big_kernel<M, 4>;
+      case 5: return newton_chord_big_kernel<M, 5>;
+      case 6: return newton_chord_big_kernel<M, 6>;
+      case 8: return newton_chord_big_kernel<M, 8>;
+      case 9: return newton_chord_big_kernel<M, 9>;
+    }
   switch (prec) {
     case 1: return big_prec_pick<M, 1>(T);
     case 2: return big_prec_pick<M, 2>(T);
@@ -62,6 +72,15 @@ const void* big_batched_prec_pick(int T) {
 
 template <int M>
 const void* big_batched_pick(int T, int prec) {
+  if (prec == 10) switch (T) {
+      case 1: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 1>);
+      case 2: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 2>);
+      case 4: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 4>);
+      case 5: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 5>);
+      case 6: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 6>);
+      case 8: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 8>);
+      case 9: return reinterpret_cast<const void*>(newton_chord_big_batched<M, 9>);
+    }
   switch (prec) {
     case 1: return big_batched_prec_pick<M, 1>(T);
     case 2: return big_batched_prec_pick<M, 2>(T);
