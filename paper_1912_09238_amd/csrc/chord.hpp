@@ -14,9 +14,10 @@
 // the nodes stream through in chunks, node by node in ascending order; the
 // matrix-vector sum over columns in ascending order).  A cell whose inverse
 // is missing, or whose step fails to contract the dual residual by theta,
-// is marked pending (hinv_ok = 2) with its dual written back; the full
-// kernel, launched next over the same list in pending mode, continues it
-// from there with a fresh Hessian.  Layout: a group of G = NP lanes per
+// is handed on (hinv_ok = 2, appended to the class's list of handed-on
+// cells) with its dual written back; the full kernel, launched next in
+// pending mode over that list, continues it from there with a fresh
+// Hessian.  Layout: a group of G = NP lanes per
 // cell, lane r holds unknown r = i M + a.
 #pragma once
 
@@ -42,6 +43,14 @@ struct ChordCfg {
                              2 * static_cast<size_t>(waves) * (CPW + 1));
   }
 };
+
+// Hand a cell on to the full kernel: marked (hinv_ok = 2, no valid inverse)
+// and appended to its class's list for this step.
+__device__ __forceinline__ void hand_on(const DualParams& P, int cell) {
+  P.hinv_ok[cell] = 2;
+  const unsigned k = atomicAdd(&P.ctrl->pend_len[P.parity][P.cls], 1u);
+  P.pend_list[k] = cell;
+}
 
 // Ansatz value u_s(lambda^T phi(xi_q)) of one node (no Jacobian).
 template <int M>
@@ -75,7 +84,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   // a cell without a valid stored inverse goes to the full kernel at once
   if (cell >= 0 && P.hinv_ok[cell] != 1) {
-    if (r == 0) P.hinv_ok[cell] = 2;
+    if (r == 0) hand_on(P, cell);
     cell = -1;
   }
   if (!__syncthreads_or(cell >= 0)) return;
@@ -223,7 +232,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     // final dual (once more, node by node) and the wave speeds
     if (live) P.lam[gidx] = lam;
     if (pending || status) {
-      if (r == 0 && pending) P.hinv_ok[cell] = 2;
+      if (r == 0 && pending) hand_on(P, cell);
     } else {
       for (int q = r; q < Q; q += G) {
         double u[M], ss;

@@ -51,7 +51,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
   if (stop) return;  // uniform
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
   if (cell >= 0 && P.hinv_ok[cell] != 1) {
-    if (lane == 0) P.hinv_ok[cell] = 2;
+    if (lane == 0) hand_on(P, cell);
     cell = -1;
   }
   if (!__syncthreads_or(cell >= 0)) return;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     for (int s = 0; s < 4; ++s)
       if (live[s]) P.lam[gidx[s]] = lam[s];
     if (pending || status) {
-      if (lane == 0 && pending) P.hinv_ok[cell] = 2;
+      if (lane == 0 && pending) hand_on(P, cell);
     } else {
       for (int q = lane; q < Q; q += 64) {
         double u[M];

@@ -76,6 +76,8 @@ struct StepCtrl {
   // [parity][class][slot * kSlotStride] lengths of the 64 lists per size
   // class of cells that need Newton steps
   unsigned int list_len[2 * kCls * kSlots * kSlotStride];
+  // [parity][class] cells the chord kernels handed on to the full kernel
+  unsigned int pend_len[2][kCls];
 };
 
 __host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) {
@@ -85,9 +87,9 @@ __host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) 
 
 // Counters per Newton block (cumulative over steps).
 constexpr int kBlkStats = 4;
-// Pending mode (after a chord kernel): few cells remain, so a block walks
-// this many blocks' worth of work items instead of one.
-constexpr int kPendItems = 16;
+// Pending mode (after a chord kernel): a launch of this many blocks per
+// problem walks the class's list of handed-on cells.
+constexpr int kPendBlocks = 32;
 
 struct DualParams {
   const double* __restrict__ phi;   // [Q][kp] Phi, zero padded to kp columns
@@ -95,6 +97,7 @@ struct DualParams {
   int N, Q, kp, cells;
   int kl;                           // Phi columns staged in LDS for this launch's class (<= kp)
   int pend;                         // full kernel after the chord kernel: pending cells only
+  int* __restrict__ pend_list;      // [class cells] cells handed on (chord kernels append)
   const int8_t* __restrict__ cellN; // modes per cell, or null (all N)
   const double* __restrict__ uhat;  // [cells][M][N]
   double* __restrict__ lam;         // [cells][M][N], in/out
@@ -329,6 +332,10 @@ typedef const __attribute__((address_space(4))) double* const_dptr;
 // first items of the grid whatever their spread over the lists), or the
 // class's cells in ascending order.  Called by every thread of the block.
 __device__ __forceinline__ int work_cell(const DualParams& P, int item) {
+  if (P.pend) {  // the cells the chord kernel of this step handed on
+    const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
+    return item < n ? P.pend_list[item] : -1;
+  }
   if (P.list_cap > 0) {
     __shared__ int pre[kSlots + 1];
     if (threadIdx.x < 64) {
@@ -364,6 +371,7 @@ __device__ __forceinline__ void reset_next_step(const DualParams& P) {
   }
   for (int k = threadIdx.x; k < kCls * kSlots; k += blockDim.x)
     C->list_len[list_len_index(P.parity ^ 1, k / kSlots, k % kSlots)] = 0u;
+  for (int k = threadIdx.x; k < kCls; k += blockDim.x) C->pend_len[P.parity ^ 1][k] = 0u;
 }
 
 template <int M, int NP, int PREC = 0>
@@ -383,8 +391,6 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   if (stop) return;  // uniform
   // the flux update of this step fills the next step's speed slots and lists
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
-  // pending mode: only the cells the chord kernel handed on (chord.hpp)
-  if (P.pend && cell >= 0 && P.hinv_ok[cell] != 2) cell = -1;
   if (!__syncthreads_or(cell >= 0)) return;
 
   // kp: LDS stride of the staged table (the class's columns), kg: the
@@ -952,9 +958,11 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 template <int M, int NP, int PREC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
 void newton_kernel(DualParams P) {
-  if (P.pend) {
-    for (int j = 0; j < kPendItems; ++j) {
-      newton_body<M, NP, PREC>(P, blockIdx.x * kPendItems + j);
+  if (P.pend) {  // the handed-on cells, block by block
+    const int cpb = (blockDim.x >> 6) * NewtonCfg<M, NP>::CPW;
+    const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
+    for (int vb = blockIdx.x; vb * cpb < n; vb += gridDim.x) {
+      newton_body<M, NP, PREC>(P, vb);
       __syncthreads();
     }
     return;
@@ -1005,8 +1013,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 
 void newton_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
   if (PP[k].pend) {
-    for (int j = 0; j < kPendItems; ++j) {
-      newton_body<M, NP, PREC>(PP[k], (blockIdx.x - begin[k]) * kPendItems + j);
+    const DualParams& P = PP[k];
+    const int cpb = (blockDim.x >> 6) * NewtonCfg<M, NP>::CPW;
+    const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
+    for (int vb = blockIdx.x - begin[k]; vb * cpb < n; vb += kPendBlocks) {
+      newton_body<M, NP, PREC>(P, vb);
       __syncthreads();
     }
     return;

@@ -108,8 +108,6 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
   int cell = work_cell(P, blk);
   if (stop) return;  // uniform
   if (P.mode == 0 && P.reset_next && blk == 0) reset_next_step(P);
-  // pending mode: only the cells the chord kernel handed on (chord_big.hpp)
-  if (P.pend && cell >= 0 && P.hinv_ok[cell] != 2) cell = -1;
   if (cell < 0) return;  // uniform over the workgroup
 
   // kp: LDS stride of the staged table (the class's columns), kg: the
@@ -574,9 +572,10 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 template <int M, int T, int PREC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
 void newton_big_kernel(DualParams P) {
-  if (P.pend) {  // after the chord kernel: a block walks kPendItems cells
-    for (int j = 0; j < kPendItems; ++j) {
-      newton_big_body<M, T, PREC>(P, blockIdx.x * kPendItems + j);
+  if (P.pend) {  // after the chord kernel: the handed-on cells
+    const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
+    for (int vb = blockIdx.x; vb < n; vb += gridDim.x) {
+      newton_big_body<M, T, PREC>(P, vb);
       __syncthreads();
     }
     return;
@@ -590,8 +589,10 @@ void newton_big_batched(const DualParams* __restrict__ PP,
                                                           const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
   if (PP[k].pend) {
-    for (int j = 0; j < kPendItems; ++j) {
-      newton_big_body<M, T, PREC>(PP[k], (blockIdx.x - begin[k]) * kPendItems + j);
+    const DualParams& P = PP[k];
+    const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
+    for (int vb = blockIdx.x - begin[k]; vb < n; vb += kPendBlocks) {
+      newton_big_body<M, T, PREC>(P, vb);
       __syncthreads();
     }
     return;

@@ -58,6 +58,7 @@ struct DualClass {
   int chord_waves = 4;
   size_t chord_lds = 0;
   int cblk_off = 0, cblk_cnt = 0;  // the chord kernel's block statistics
+  int* d_pend = nullptr;            // [count] cells the chord kernel hands on
 };
 
 // Problems up to this many cells are latency bound: one Newton launch for
@@ -401,6 +402,7 @@ void free_problem(Problem* P) {
     if (c.d_lists) (void)hipFree(c.d_lists);
     if (c.d_order) (void)hipFree(c.d_order);
     if (c.d_hinv) (void)hipFree(c.d_hinv);
+    if (c.d_pend) (void)hipFree(c.d_pend);
   }
 }
 
@@ -637,11 +639,13 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
   // set-up runs the exact-Newton variant
   const int prec = ghost_cells >= 0 ? (D.prec & 1) : D.prec;
   if (prec & 2) P.set_hinv(d, D);
+  bool pend = false;
   if (D.chord && ghost_cells < 0 && d.mode == 0) {
     // chord steps first (own block statistics), then the full kernel over
     // the cells they handed on
     DualParams dc = d;
     dc.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
+    dc.pend_list = D.d_pend;
     DualFn cf = D.T > 0 ? pick_big(P.M, D.T, 10) : pick_dual(P.M, D.NP, 10);
     if (!cf) return fail(ctx, IPM_E_ARG, "no chord kernel for this size");
     const int cpb = D.chord_waves * (D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP));
@@ -649,18 +653,19 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
                        ctx->stream, dc);
     HIPCHK(ctx, hipGetLastError());
     d.pend = 1;
+    d.pend_list = D.d_pend;
     d.reset_next = 0;
+    pend = true;
   }
-  const int pk = d.pend ? kPendItems : 1;  // pending mode: blocks walk several items
   if (D.T > 0) {
     DualFn fn = pick_big(P.M, D.T, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-    hipLaunchKernelGGL(fn, dim3((items + pk - 1) / pk), dim3(256), D.lds, ctx->stream, d);
+    hipLaunchKernelGGL(fn, dim3(pend ? kPendBlocks : items), dim3(256), D.lds, ctx->stream, d);
   } else {
     DualFn fn = pick_dual(P.M, D.NP, prec);
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
-    const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP) * pk;
-    const int blocks = (items + per_block - 1) / per_block;
+    const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP);
+    const int blocks = pend ? kPendBlocks : (items + per_block - 1) / per_block;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * D.waves), D.lds, ctx->stream, d);
   }
   HIPCHK(ctx, hipGetLastError());
@@ -862,6 +867,7 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
           // kernel over the cells it hands on
           DualParams dk = dc;
           dk.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
+          dk.pend_list = D.d_pend;
           const int cpb = D.chord_waves * (D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP));
           const std::string ck = "0:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                  std::to_string(D.T) + ":" + std::to_string(64 * D.chord_waves);
@@ -870,16 +876,19 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
           nkind[ck] = {P.M, D.NP, D.T > 0 ? 1 : 0, 10};
           nfn[ck] = pick_newton_batched(P.M, D.NP, D.T, 10);
           if (!nfn[ck]) return fail(ctx, IPM_E_ARG, "no batched chord kernel for this size");
+          // pending mode: a fixed grid over the handed-on cells
           dc.pend = 1;
+          dc.pend_list = D.d_pend;
           dc.reset_next = 0;
+          dc.lists = nullptr;
+          dc.list_cap = 0;
         }
-        const int per_block = (D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP)) *
-                              (dc.pend ? kPendItems : 1);
+        const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
         const std::string key = "1:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                 std::to_string(D.T) + ":" + std::to_string(threads) + ":" +
                                 std::to_string(D.prec) + (dc.pend ? ":p" : "");
-        ng[key].push_back({dc, (items + per_block - 1) / per_block, D.lds});
+        ng[key].push_back({dc, dc.pend ? kPendBlocks : (items + per_block - 1) / per_block, D.lds});
         nshape[key] = {threads, per_block};
         nkind[key] = {P.M, D.NP, D.T > 0 ? 1 : 0, D.prec};
         nfn[key] = pick_newton_batched(P.M, D.NP, D.T, D.prec);
@@ -1539,6 +1548,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   ALLOC(P.d_blk, static_cast<size_t>(P.dual_blocks) * kBlkStats * sizeof(unsigned long long));
   for (DualClass& D : P.cls) {
     if (D.cap > 0) ALLOC(D.d_lists, 2 * static_cast<size_t>(kSlots) * D.cap * sizeof(int));
+    if (D.chord) ALLOC(D.d_pend, static_cast<size_t>(D.count) * sizeof(int));
     if (P.uneven && D.order_len > 0) ALLOC(D.d_order, static_cast<size_t>(D.order_len) * sizeof(int));
   }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
