@@ -35,10 +35,14 @@ struct ChordCfg {
   __host__ __device__ static int chunk(int Q) { return Q < G ? Q : G; }
   // per group: dual [NP], ansatz [CH][M]
   __host__ __device__ static int group_doubles(int Q) { return NP + chunk(Q) * M; }
-  // tables Phi [Q][kl] and w [Q], the groups' areas, 2 stats per group and 2
-  // speeds per wavefront
+  // node stride of the tables, which are stored mode by mode (a node per
+  // lane reads consecutive words); odd, so that lanes of different modes
+  // read different banks
+  __host__ __device__ static int qstride(int Q) { return Q | 1; }
+  // tables Phi and w Phi [kl][Q|1] and w [Q], the groups' areas, 2 stats per
+  // group and 2 speeds per wavefront
   __host__ __device__ static size_t lds_bytes(int Q, int kl, int waves) {
-    return sizeof(double) * (static_cast<size_t>(Q) * kl + Q +
+    return sizeof(double) * (2 * static_cast<size_t>(kl) * qstride(Q) + Q +
                              static_cast<size_t>(waves) * CPW * group_doubles(Q) +
                              2 * static_cast<size_t>(waves) * (CPW + 1));
   }
@@ -52,17 +56,19 @@ __device__ __forceinline__ void hand_on(const DualParams& P, int cell) {
   P.pend_list[k] = cell;
 }
 
-// Ansatz value u_s(lambda^T phi(xi_q)) of one node (no Jacobian).
+// Ansatz value u_s(lambda^T phi(xi_q)) of one node (no Jacobian); phi_i(q)
+// at ph[i * stride].
 template <int M>
 __device__ __forceinline__ bool node_ansatz(const DualParams& P, const double* lamS, int Nc,
-                                            const double* ph, double (&u)[M], double& ss) {
+                                            const double* ph, int stride, double (&u)[M],
+                                            double& ss) {
   constexpr int NJ = M * (M + 1) / 2;
   double L[M], J[NJ];
 #pragma unroll
   for (int a = 0; a < M; ++a) L[a] = 0.0;
 #pragma unroll 4
   for (int i = 0; i < Nc; ++i) {
-    const double f = ph[i];
+    const double f = ph[i * stride];
 #pragma unroll
     for (int a = 0; a < M; ++a) L[a] = fma(lamS[i * M + a], f, L[a]);
   }
@@ -98,14 +104,21 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   double lam = live ? P.lam[gidx] : 0.0;
   const double uh = live ? P.uhat[gidx] : 0.0;
   extern __shared__ double smem[];
-  double* phiL = smem;         // [Q][kp]
-  double* wL = phiL + Q * kp;  // [Q]
-  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) phiL[k] = P.phi[(k / kp) * kg + k % kp];
+  const int QT = Cfg::qstride(Q);
+  double* phiT = smem;             // [kp][QT]: phi_i(q)
+  double* wphiT = phiT + kp * QT;  // [kp][QT]: w_q phi_i(q)
+  double* wL = wphiT + kp * QT;    // [Q]
+  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) {
+    const int q = k / kp, i = k % kp;
+    phiT[i * QT + q] = P.phi[q * kg + i];
+    wphiT[i * QT + q] = P.wphi[q * kg + i];
+  }
   for (int q = threadIdx.x; q < Q; q += blockDim.x) wL[q] = P.wphi[static_cast<size_t>(q) * kg];
   const int CH = Cfg::chunk(Q);
-  double* lamS = wL + Q + static_cast<size_t>(wave * CPW + grp) * Cfg::group_doubles(Q);  // [NP]
-  double* US = lamS + NP;                                                                 // [CH][M]
-  double* stats = wL + Q + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
+  double* areas = wL + Q;
+  double* lamS = areas + static_cast<size_t>(wave * CPW + grp) * Cfg::group_doubles(Q);  // [NP]
+  double* US = lamS + NP;                                                                // [CH][M]
+  double* stats = areas + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
   __syncthreads();
 
   int its = 0;
@@ -129,16 +142,19 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
         const int q = c0 + r;
         if (q < Q) {
           double u[M], ss;
-          okp &= node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss) ? 1 : 0;
+          okp &= node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss) ? 1 : 0;
 #pragma unroll
           for (int a = 0; a < M; ++a) US[r * M + a] = u[a];
           ssum = fma(wL[q], ss, ssum);
         }
         wave_sync();
         const int nq = Q - c0 < CH ? Q - c0 : CH;
-        if (live)
-          for (int j = 0; j < nq; ++j)
-            gacc = fma(US[j * M + aa], wL[c0 + j] * phiL[(c0 + j) * kp + ii], gacc);
+        // w_q phi_i(q) is the product the host formed once (phi_0 = 1, so
+        // wL holds w_q exactly and the terms equal wL[q] * phi_i(q))
+        if (live) {
+          const double* wr = wphiT + ii * QT + c0;
+          for (int j = 0; j < nq; ++j) gacc = fma(US[j * M + aa], wr[j], gacc);
+        }
         wave_sync();
       }
       return okp;
@@ -170,9 +186,18 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       // ---- d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area
       lamS[r] = g;
       wave_sync();
+      // the stored entries of 16 columns requested at once, then summed in
+      // ascending column order
       double acc = 0.0;
       if (live)
-        for (int c = 0; c < nc; ++c) acc = fma(Hc[c * NP + r], lamS[c], acc);
+        for (int c0 = 0; c0 < nc; c0 += 16) {
+          double h[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) h[j] = c0 + j < nc ? Hc[(c0 + j) * NP + r] : 0.0;
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (c0 + j < nc) acc = fma(h[j], lamS[c0 + j], acc);
+        }
       const double d = live ? -acc : 0.0;
       wave_sync();
       // ---- step length (as the full kernel: backtracking while far from tau)
@@ -236,7 +261,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     } else {
       for (int q = r; q < Q; q += G) {
         double u[M], ss;
-        (void)node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss);
+        (void)node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss);
 #pragma unroll
         for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
         double ax, ay;

@@ -26,10 +26,13 @@ struct ChordBigCfg {
   static constexpr int NJ = M * (M + 1) / 2;
   // per cell: dual [NPB], ansatz [Q][M], gradient [NPB], step [NPB]
   __host__ __device__ static int cell_doubles(int Q) { return 3 * NPB + Q * M; }
-  // tables Phi [Q][kl] and w [Q], the cells' areas, 2 stats per cell and 2
+  // node stride of the table, stored mode by mode (odd: lanes of different
+  // modes read different banks)
+  __host__ __device__ static int qstride(int Q) { return Q | 1; }
+  // tables Phi [kl][Q|1] and w [Q], the cells' areas, 2 stats per cell and 2
   // speeds per wavefront
   __host__ __device__ static size_t lds_bytes(int Q, int kl, int waves) {
-    return sizeof(double) * (static_cast<size_t>(Q) * kl + Q +
+    return sizeof(double) * (static_cast<size_t>(kl) * qstride(Q) + Q +
                              static_cast<size_t>(waves) * (cell_doubles(Q) + 4));
   }
 };
@@ -58,9 +61,11 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
 
   const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
   extern __shared__ double smem[];
-  double* phiL = smem;         // [Q][kp]
-  double* wL = phiL + Q * kp;  // [Q]
-  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) phiL[k] = P.phi[(k / kp) * kg + k % kp];
+  const int QT = Cfg::qstride(Q);
+  double* phiT = smem;            // [kp][QT]: phi_i(q)
+  double* wL = phiT + kp * QT;    // [Q]
+  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x)
+    phiT[(k % kp) * QT + k / kp] = P.phi[(k / kp) * kg + k % kp];
   for (int q = threadIdx.x; q < Q; q += blockDim.x) wL[q] = P.wphi[static_cast<size_t>(q) * kg];
   double* lamS = wL + Q + static_cast<size_t>(wave) * (Cfg::cell_doubles(Q) + 4);
   double* US = lamS + NPB;   // [Q][M]
@@ -104,7 +109,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         const int q = lane + 64 * s;
         if (q < Q) {
           double u[M], ss;
-          okp &= node_ansatz<M>(P, lamS, Nc, phiL + q * kp, u, ss) ? 1 : 0;
+          okp &= node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss) ? 1 : 0;
 #pragma unroll
           for (int a = 0; a < M; ++a) US[q * M + a] = u[a];
           ssum[s] = fma(wL[q], ss, ssum[s]);
@@ -120,7 +125,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       for (int s = 0; s < 4; ++s) {
         double gg = 0.0;
         if (live[s]) {
-          for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra[s]] * wL[q], phiL[q * kp + ri[s]], gg);
+          const double* pr = phiT + ri[s] * QT;
+          for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra[s]] * wL[q], pr[q], gg);
           gg -= uh[s];
         }
         g[s] = gg;

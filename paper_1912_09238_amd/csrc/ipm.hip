@@ -55,6 +55,7 @@ struct DualClass {
   // register-row inexact-Hessian classes: chord steps in a kernel of their
   // own, then the full kernel over the cells it handed on
   bool chord = false;
+  int chord_kl = 1;         // table columns the chord kernel stages (its cells' modes)
   int chord_waves = 4;
   size_t chord_lds = 0;
   int cblk_off = 0, cblk_cnt = 0;  // the chord kernel's block statistics
@@ -67,6 +68,7 @@ constexpr int kMergeCells = 32768;
 
 struct Problem {
   int eq = 0, M = 1, dim = 1, p = 1, degree = 0, N = 1, Q = 1, kp = 1, UG = 16;
+  int cls_modes[kCls] = {};  // most modes of a cell in each size class (before merging)
   int full_cls = 0;  // class of a cell with all N modes (ghosts)
   DualClass cls[kCls];
   int nx = 1, ny = 1, cells = 1;
@@ -559,7 +561,13 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
     // (workgroup classes: one node per stand-in thread, so Q <= 256)
     D.chord = (D.prec & 2) && !P.adapt && D.count > 0 && !D.merged && (D.T == 0 || P.Q <= 256);
     if (D.chord) {
-      const int kl = class_kl(P.M, P.kp, D.NP, D.T);
+      // the chord kernel stages the modes of the cells it takes (its own and
+      // those of classes merged into it), not the class's padded rows
+      int modes = 0;
+      for (int k = 0; k <= c; ++k)
+        if (static_cast<int>((P.cls_map >> (4 * k)) & 15u) == c) modes = std::max(modes, P.cls_modes[k]);
+      D.chord_kl = std::max(1, std::min(class_kl(P.M, P.kp, D.NP, D.T), modes));
+      const int kl = D.chord_kl;
       auto lds_for = [&](int w) {
         return D.T > 0 ? chord_big_lds_bytes(P.M, D.T, P.Q, kl, w)
                        : chord_lds_bytes(P.M, D.NP, P.Q, kl, w);
@@ -644,6 +652,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     // chord steps first (own block statistics), then the full kernel over
     // the cells they handed on
     DualParams dc = d;
+    dc.kl = D.chord_kl;
     dc.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
     dc.pend_list = D.d_pend;
     DualFn cf = D.T > 0 ? pick_big(P.M, D.T, 10) : pick_dual(P.M, D.NP, 10);
@@ -866,6 +875,7 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
           // stage 0: the chord kernel (own statistics); stage 1: the full
           // kernel over the cells it hands on
           DualParams dk = dc;
+          dk.kl = D.chord_kl;
           dk.blk_stats = P.d_blk + kBlkStats * static_cast<size_t>(D.cblk_off);
           dk.pend_list = D.d_pend;
           const int cpb = D.chord_waves * (D.T > 0 ? 1 : dual_cells_per_wave(P.M, D.NP));
@@ -1463,10 +1473,12 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
       cellN[c] = static_cast<int8_t>(binom_basis(pb->p, dg));
       cell_cls[c] = size_class(cellN[c] * P.M);
       ++counts[cell_cls[c]];
+      P.cls_modes[cell_cls[c]] = std::max(P.cls_modes[cell_cls[c]], static_cast<int>(cellN[c]));
     }
     P.uneven = true;
   } else {
     counts[size_class(P.M * P.N)] = P.cells;
+    P.cls_modes[size_class(P.M * P.N)] = P.N;
   }
   int plan_counts[kCls];
   for (int c = 0; c < kCls; ++c) plan_counts[c] = counts[c];
