@@ -307,44 +307,111 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
       lc = P.lam + static_cast<size_t>(cell) * N;
       le = P.lam + static_cast<size_t>(neighbour_1d(P, ix, 1)) * N;
     }
-    for (int k = r; k < M * N; k += G) {
-      const int b = k / N, i = k % N;
-      double v = 0.0, h = 0.0;
-      if (i < Nn)
-        for (int q = 0; q < Q; ++q) {
-          const double w = wphiL[q * kp + i];
-          v = fma(ut[q * M + b], w, v);
-          h = fma(uq[q * M + b], w, h);
-        }
-      if (analytic && i < Nn) {
-        // App. A, eq:numFluxAnalytic on the duals (quadratic entropy: the
-        // dual is the SG moment vector): F_i(u) = u^T C_i u / 2,
-        // G = (F(u_l) + F(u_r)) / 2 - dx / (2 dt) (u_r - u_l)
-        double fw = 0.0, fc = 0.0, fe = 0.0;
-        for (int a = 0; a < N; ++a) {
-          const double* Ca = ctpL + (static_cast<size_t>(i) * N + a) * N;
-          double sw = 0.0, sc = 0.0, se = 0.0;
-          for (int bb = 0; bb < N; ++bb) {
-            sw = fma(Ca[bb], lw[bb], sw);
-            sc = fma(Ca[bb], lc[bb], sc);
-            se = fma(Ca[bb], le[bb], se);
+    if (analytic) {
+      for (int k = r; k < M * N; k += G) {
+        const int b = k / N, i = k % N;
+        double v = 0.0, h = 0.0;
+        if (i < Nn)
+          for (int q = 0; q < Q; ++q) {
+            const double w = wphiL[q * kp + i];
+            v = fma(ut[q * M + b], w, v);
+            h = fma(uq[q * M + b], w, h);
           }
-          fw = fma(0.5 * sw, lw[a], fw);
-          fc = fma(0.5 * sc, lc[a], fc);
-          fe = fma(0.5 * se, le[a], fe);
+        if (i < Nn) {
+          // App. A, eq:numFluxAnalytic on the duals (quadratic entropy: the
+          // dual is the SG moment vector): F_i(u) = u^T C_i u / 2,
+          // G = (F(u_l) + F(u_r)) / 2 - dx / (2 dt) (u_r - u_l)
+          double fw = 0.0, fc = 0.0, fe = 0.0;
+          for (int a = 0; a < N; ++a) {
+            const double* Ca = ctpL + (static_cast<size_t>(i) * N + a) * N;
+            double sw = 0.0, sc = 0.0, se = 0.0;
+            for (int bb = 0; bb < N; ++bb) {
+              sw = fma(Ca[bb], lw[bb], sw);
+              sc = fma(Ca[bb], lc[bb], sc);
+              se = fma(Ca[bb], le[bb], se);
+            }
+            fw = fma(0.5 * sw, lw[a], fw);
+            fc = fma(0.5 * sc, lc[a], fc);
+            fe = fma(0.5 * se, le[a], fe);
+          }
+          const double gr = 0.5 * (fc + fe) - lfx * (le[i] - lc[i]);
+          const double gl = 0.5 * (fw + fc) - lfx * (lc[i] - lw[i]);
+          v = lc[i] - dt / P.dx * (gr - gl);
         }
-        const double gr = 0.5 * (fc + fe) - lfx * (le[i] - lc[i]);
-        const double gl = 0.5 * (fw + fc) - lfx * (lc[i] - lw[i]);
-        v = lc[i] - dt / P.dx * (gr - gl);
-      }
-      const size_t off = static_cast<size_t>(cell) * M * N + k;
-      const double d = v - (k == r ? uold0 : P.uold[off]);
-      d2 = fma(d, d, d2);
-      finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
-      P.unew[off] = v;
-      const double g = h - v;  // next step's dual gradient at its warm start
+        const size_t off = static_cast<size_t>(cell) * M * N + k;
+        const double d = v - (k == r ? uold0 : P.uold[off]);
+        d2 = fma(d, d, d2);
+        finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
+        P.unew[off] = v;
+        const double g = h - v;  // next step's dual gradient at its warm start
 #pragma unroll
-      for (int bb = 0; bb < M; ++bb) gsq[bb] += (bb == b) ? g * g : 0.0;
+        for (int bb = 0; bb < M; ++bb) gsq[bb] += (bb == b) ? g * g : 0.0;
+      }
+    } else {
+      // projection on the Nn modes of the cell's level: lane r takes mode
+      // i = r mod Nn for every variable, over the nodes q = s, s + S, ...
+      // of its node group s = r / Nn (S groups, a power of two); the groups
+      // are then added pairwise (s takes s + o, o = S/2, ..., 1).  Wide
+      // levels (Nn > G) take modes r, r + G, ... over all nodes.
+      const bool wide = Nn > G;
+      int S = 1;
+      if (!wide)
+        while (2 * S * Nn <= G) S *= 2;
+      int Smax = 1;  // uniform over the wavefront, so every lane joins each exchange
+      for (int e = 1; e <= 6; ++e)
+        if (__ballot(S >= (1 << e)) != 0ull) Smax = 1 << e;
+      const int rounds = wide ? (Nn + G - 1) / G : 1;
+      for (int t = 0; t < rounds; ++t) {
+        const int i = wide ? r + t * G : r % Nn;
+        const int sg = wide ? 0 : r / Nn;
+        const bool act = wide ? i < Nn : sg < S;
+        double v[M], h[M];
+#pragma unroll
+        for (int b = 0; b < M; ++b) v[b] = h[b] = 0.0;
+        if (act)
+          for (int q = sg; q < Q; q += S) {
+            const double w = wphiL[q * kp + i];
+#pragma unroll
+            for (int b = 0; b < M; ++b) {
+              v[b] = fma(ut[q * M + b], w, v[b]);
+              h[b] = fma(uq[q * M + b], w, h[b]);
+            }
+          }
+        for (int o = Smax >> 1; o >= 1; o >>= 1) {
+          const bool take = sg < o && sg + o < S;
+          const int src = take ? lane + o * Nn : lane;
+#pragma unroll
+          for (int b = 0; b < M; ++b) {
+            const double pv = __shfl(v[b], src, 64);
+            const double ph = __shfl(h[b], src, 64);
+            if (take) {
+              v[b] += pv;
+              h[b] += ph;
+            }
+          }
+        }
+        if (act && sg == 0) {
+#pragma unroll
+          for (int b = 0; b < M; ++b) {
+            const size_t off = static_cast<size_t>(cell) * M * N + static_cast<size_t>(b) * N + i;
+            const double d = v[b] - P.uold[off];
+            d2 = fma(d, d, d2);
+            finite &= (v[b] == v[b] && fabs(v[b]) < 1e300) ? 1 : 0;
+            P.unew[off] = v[b];
+            const double g = h[b] - v[b];  // next step's dual gradient at its warm start
+            gsq[b] = fma(g, g, gsq[b]);
+          }
+        }
+      }
+      // modes above the level: zero (a lowered cell's old moments there
+      // enter the residual)
+      const int nz = N - Nn;
+      for (int k = r; k < M * nz; k += G) {
+        const size_t off = static_cast<size_t>(cell) * M * N + static_cast<size_t>(k / nz) * N + Nn + k % nz;
+        const double d = P.uold[off];
+        d2 = fma(d, d, d2);
+        P.unew[off] = 0.0;
+      }
     }
     d2 = group_sum<G>(d2);
     res_cell = P.vol * sqrt(d2);
