@@ -8,7 +8,7 @@ Gauss-Legendre nodes, Euler entropy, Rusanov, CFL 0.5 -- stepped together
 is one IPM time step of every problem: for every cell the dual Newton solve
 to tau = 1e-10, the kinetic flux at the nodes and the moment update.  The
 value is the mixed-precision form (Hessian on the matrix cores in split BF16
-with FP32 accumulation, stored FP64 inverse Hessians reused while they
+with FP32 accumulation, stored FP32 inverse Hessians reused while they
 contract, FP64 gradient, tau test and solve); beside it the plain FP64 form
 and the FP64 form with stored inverses, on the same steps from the same
 states.  Inputs are resident in HBM before timing starts.
@@ -98,10 +98,10 @@ def class_bytes(n, m, Q, listed, iterations, fresh, variant):
     """Algorithmic HBM bytes of a size class's Newton work: per solved cell
     the dual and the moments read, the dual and the nodal ansatz written;
     with stored inverses (variant bit 1) each step from a stored inverse
-    reads its n x n entries and each fresh one writes them."""
+    reads its n x n FP32 entries and each fresh one writes them."""
     b = listed * (3 * n + Q * m) * 8
     if variant & 2:
-        b += iterations * n * n * 8
+        b += iterations * n * n * 4
     return b
 
 
@@ -169,7 +169,7 @@ def batch_form(args):
         ctx.release(pid)
     # the same problems, same warm-up and timed steps from the same initial
     # states, in the mixed-precision form (BF16 MFMA Hessians, inexact-Hessian
-    # Newton with FP64 inverses reused on every cell, FP64 tau test) and in the
+    # Newton with FP32 inverses reused on every cell, FP64 tau test) and in the
     # inexact-Hessian form alone (FP64 Hessians)
     forms = {}
     for fname, extra, label in (
@@ -452,11 +452,11 @@ def headline_form(args):
         "metric": METRIC, "value": mixed["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+bf16", "data": "synthetic",
+        "dtype": "f64+f32+bf16", "data": "synthetic",
         "config": {"workload": "batch64_euler2d_p3_deg1to4_q125_mixed_precision",
                    "problems": len(specs), "cells": cells,
                    "cells_by_degree": {str(k): int(hist[k]) for k in range(1, 5)},
-                   "form": "BF16-split MFMA Hessian (cells of 65..96 unknowns) + stored FP64 "
+                   "form": "BF16-split MFMA Hessian (cells of 65..96 unknowns) + stored FP32 "
                            "inverse Hessians on every cell; FP64 gradient, tau test, solve",
                    "parallelism": "single-gpu"},
         "roofline": roof,
@@ -494,7 +494,7 @@ def precision_form(args):
     """Precision form: 2D Euler bump on a periodic 512 x 512 grid, two
     uncertainties, total degree 5 (21 modes, 84 unknowns per cell), 8 x 8
     nodes, the same steps in the plain FP64 form (exact Newton), with the
-    split-BF16 MFMA Hessian, and with the inexact-Hessian Newton (stored FP64
+    split-BF16 MFMA Hessian, and with the inexact-Hessian Newton (stored FP32
     inverse Hessians reused while they contract) in FP64 and with the BF16
     Hessian.  The tau test stays FP64 in every variant; the line reports the
     BF16 + reuse variant and the relative L1 difference of E and Var of every
@@ -542,7 +542,7 @@ def precision_form(args):
         "metric": METRIC, "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.prec_steps, "warmup": args.prec_warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16-mfma-hessian+fp64-inverse-reuse/f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16-mfma-hessian+fp32-inverse-reuse/f64", "data": "synthetic",
         "config": {"workload": "euler2d_bump_%dx%d_deg5_q64" % (args.prec_n, args.prec_n),
                    "cells": cells, "n": 84, "Q": 64, "parallelism": "single-gpu"},
         "speedup_vs_fp64": r["speedup_vs_fp64"],

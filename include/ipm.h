@@ -153,9 +153,9 @@ typedef struct {
      Hessian at every iteration) for the cells on the workgroup kernel (more
      than 64 unknowns, or many quadrature nodes): 1 = each such cell keeps
      the inverse of its last freshly assembled Hessian in device memory
-     (FP64, NP x NP doubles with NP = n rounded up to 8, 16, 32 or 64 for
-     n <= 64 and to a multiple of 16 above: 8 KB per cell at n = 30, about
-     74 KB at n = 84) and takes later
+     (rounded to FP32, NP x NP floats with NP = n rounded up to 8, 16, 32 or
+     64 for n <= 64 and to a multiple of 16 above: 4 KB per cell at n = 30,
+     about 37 KB at n = 84) and takes later
      Newton steps, in this and following time steps, as d = H_old^-1 grad L
      while each such step contracts the dual residual by reuse_theta;
      otherwise the inverse is retired and the next iteration (one-shot: of

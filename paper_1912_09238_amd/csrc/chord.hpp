@@ -128,7 +128,8 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   if (cell >= 0) {
     const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
     auto group_all = [&](int v) -> int { return (__ballot(!v) & gmask) == 0ull ? 1 : 0; };
-    const double* Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
+    const global_fptr Hc =
+        (global_fptr)(P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride);
     lamS[r] = lam;
     wave_sync();
     // the nodes in chunks (lane r: node c0 + r): <s_*> and the gradient sum
@@ -186,17 +187,18 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       // ---- d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area
       lamS[r] = g;
       wave_sync();
-      // the stored entries of 16 columns requested at once, then summed in
-      // ascending column order
+      // the stored entries of 16 columns requested at once (unconditional
+      // loads: a column past nc re-reads the last one and is not summed),
+      // then summed in ascending column order
       double acc = 0.0;
       if (live)
         for (int c0 = 0; c0 < nc; c0 += 16) {
-          double h[16];
+          float h[16];
 #pragma unroll
-          for (int j = 0; j < 16; ++j) h[j] = c0 + j < nc ? Hc[(c0 + j) * NP + r] : 0.0;
+          for (int j = 0; j < 16; ++j) h[j] = Hc[min(c0 + j, nc - 1) * nc + r];
 #pragma unroll
           for (int j = 0; j < 16; ++j)
-            if (c0 + j < nc) acc = fma(h[j], lamS[c0 + j], acc);
+            if (c0 + j < nc) acc = fma(static_cast<double>(h[j]), lamS[c0 + j], acc);
         }
       const double d = live ? -acc : 0.0;
       wave_sync();

@@ -97,7 +97,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       uh[s] = live[s] ? P.uhat[gidx[s]] : 0.0;
       if (v < NPB) lamS[v] = live[s] ? lam[s] : 0.0;
     }
-    const double* Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
+    const global_fptr Hc =
+        (global_fptr)(P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride);
     wave_sync();
     double ssum[4];
     // the ansatz at node v of each stand-in thread: U to LDS, <s_*> shares
@@ -175,7 +176,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         for (int i = 0; i < T; ++i) {
           double ps = 0.0;
 #pragma unroll
-          for (int j = 0; j < T; ++j) ps = fma(Hc[(i * T + j) * 256 + u], gc[j], ps);
+          for (int j = 0; j < T; ++j) ps = fma(static_cast<double>(Hc[(i * T + j) * 256 + u]), gc[j], ps);
           double dv = 0.0;
           dv += row_bcast<0>(ps);
           dv += row_bcast<1>(ps);

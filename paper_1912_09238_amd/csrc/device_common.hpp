@@ -199,6 +199,53 @@ __device__ __forceinline__ void physical_flux(double gamma, int dir, const doubl
   speed = fabs(vn) + sqrt(gamma * p * ir);
 }
 
+// The quantities of a node state that its fluxes in every direction share
+// (gas dynamics: 1/rho, velocity, pressure and sound speed), formed with the
+// same operations as physical_flux, so fluxes and speeds built from them
+// equal physical_flux's bit for bit with one division and one square root
+// per state.
+template <int M>
+struct FluxState {
+  double ir = 0.0, p = 0.0, a = 0.0;
+  double v[2] = {0.0, 0.0};
+};
+
+template <int M>
+__device__ __forceinline__ FluxState<M> flux_state(double gamma, const double* u) {
+  FluxState<M> s;
+  if (M == 1) return s;
+  constexpr int d = M - 2;
+  const double rho = u[0];
+  s.ir = 1.0 / rho;
+  double vv = 0.0;
+#pragma unroll
+  for (int k = 0; k < d; ++k) {
+    s.v[k] = u[1 + k] * s.ir;
+    vv += s.v[k] * s.v[k];
+  }
+  s.p = (gamma - 1.0) * (u[M - 1] - 0.5 * rho * vv);
+  s.a = sqrt(gamma * s.p * s.ir);
+  return s;
+}
+
+// physical_flux from a state's shared quantities
+template <int M>
+__device__ __forceinline__ void state_flux(const FluxState<M>& s, int dir, const double* u,
+                                           double* f, double& speed) {
+  if (M == 1) {
+    f[0] = 0.5 * u[0] * u[0];
+    speed = fabs(u[0]);
+    return;
+  }
+  constexpr int d = M - 2;
+  const double vn = s.v[dir];
+  f[0] = u[0] * vn;
+#pragma unroll
+  for (int k = 0; k < d; ++k) f[1 + k] = u[1 + k] * vn + (k == dir ? s.p : 0.0);
+  f[M - 1] = (u[M - 1] + s.p) * vn;
+  speed = fabs(vn) + s.a;
+}
+
 // Wave speeds of one node state: sx (x-direction) and sy (y, 2D only).
 template <int M>
 __device__ __forceinline__ void wave_speeds(double gamma, int dim, const double* u, double& sx,
@@ -217,6 +264,20 @@ __device__ __forceinline__ void numerical_flux(int kind, double gamma, int dir, 
   double fl[M], fr[M], al, ar;
   physical_flux<M>(gamma, dir, ul, fl, al);
   physical_flux<M>(gamma, dir, ur, fr, ar);
+  const double visc = kind == kFluxLF ? lf_visc : 0.5 * fmax(al, ar);
+#pragma unroll
+  for (int a = 0; a < M; ++a) g[a] = 0.5 * (fl[a] + fr[a]) - visc * (ur[a] - ul[a]);
+}
+
+// numerical_flux from the two states' shared quantities
+template <int M>
+__device__ __forceinline__ void numerical_flux_s(int kind, int dir, const double* ul,
+                                                 const FluxState<M>& sl, const double* ur,
+                                                 const FluxState<M>& sr, double lf_visc,
+                                                 double* g) {
+  double fl[M], fr[M], al, ar;
+  state_flux<M>(sl, dir, ul, fl, al);
+  state_flux<M>(sr, dir, ur, fr, ar);
   const double visc = kind == kFluxLF ? lf_visc : 0.5 * fmax(al, ar);
 #pragma unroll
   for (int a = 0; a < M; ++a) g[a] = 0.5 * (fl[a] + fr[a]) - visc * (ur[a] - ul[a]);

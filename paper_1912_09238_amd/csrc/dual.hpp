@@ -120,11 +120,14 @@ struct DualParams {
   int order_len;
   int bcache;                       // precision form: B fragments cached in LDS
   // inexact-Hessian Newton: per cell the inverse Hessian of its last fresh
-  // assembly (workgroup kernel: [T*T][256] tiles; small kernel: rows of
-  // -H^-1 as [NP][NP] by column), and a valid flag; null: exact Newton
-  double* __restrict__ hinv;
+  // assembly (workgroup kernel: [T*T][256] tiles; small kernel: the cell's
+  // nc x nc block of -H^-1 by column, dense), and a valid flag; null: exact
+  // Newton.
+  // Stored in FP32: a stale inverse only sets the direction of a step whose
+  // gradient and tau test stay FP64, and the steps are checked to contract.
+  float* __restrict__ hinv;
   unsigned char* __restrict__ hinv_ok;      // [cells]
-  long long hinv_stride;                    // doubles per cell in hinv
+  long long hinv_stride;                    // floats per cell in hinv
   const int* __restrict__ hinv_slot;        // [cells] slot in hinv (null: the cell index)
   double reuse_theta;                       // a stale step must give res_new <= theta res_old
 };
@@ -326,6 +329,9 @@ struct NewtonCfg {
 // Read-only table through the scalar unit: the basis values of one node are
 // the same for every lane, so they need not occupy LDS bandwidth.
 typedef const __attribute__((address_space(4))) double* const_dptr;
+// Device memory read through the vector memory path (global loads: unlike
+// flat loads they do not hold up the wait for LDS results).
+typedef const __attribute__((address_space(1))) float* global_fptr;
 
 // The cell of work item `item`: the 64 lists of the launch's size class laid
 // end to end (a prefix sum over their lengths, so the listed cells occupy the
@@ -418,10 +424,13 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   extern __shared__ double smem[];
   double* phiL = smem;
   double* wphiL = phiL + Q * kp;
+  // the LDS stride is odd (a lane per node reads its own row without bank
+  // conflicts) and may exceed the global one by a zero column
   for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) {
-    const int g = (k / kp) * kg + k % kp;
-    phiL[k] = P.phi[g];
-    wphiL[k] = P.wphi[g];
+    const int i = k % kp;
+    const int g = (k / kp) * kg + i;
+    phiL[k] = i < kg ? P.phi[g] : 0.0;
+    wphiL[k] = i < kg ? P.wphi[g] : 0.0;
   }
   const const_dptr phiC = (const_dptr)(P.phi);
   const int gidx_l = wave * CPW + grp;
@@ -509,7 +518,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
     // the flag this cell writes (no re-read of its own write)
     bool have_inv = false;
     if constexpr (reuse) have_inv = P.hinv_ok[cell] == 1;  // 2: handed on without one
-    double* Hc = nullptr;  // the cell's stored rows of -H^-1, [NP][NP] by column
+    float* Hc = nullptr;  // the cell's stored block of -H^-1, [nc][nc] by column
     if constexpr (reuse)
       Hc = P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride;
 
@@ -539,7 +548,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           for (int s = 0; s < R; ++s)
 #pragma unroll
             for (int c = 0; c < NP; ++c)
-              row[s][c] = (live[s] && c < nc) ? Hc[c * NP + ro[s]] : 0.0;
+              row[s][c] = (live[s] && c < nc) ? static_cast<double>(Hc[c * nc + ro[s]]) : 0.0;
         }
       }
       if (fresh) {
@@ -682,7 +691,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           for (int s = 0; s < R; ++s)
 #pragma unroll
             for (int c = 0; c < NP; ++c)
-              if (live[s] && c < nc) Hc[c * NP + ro[s]] = row[s][c];
+              if (live[s] && c < nc) Hc[c * nc + ro[s]] = static_cast<float>(row[s][c]);
           if (r == 0) P.hinv_ok[cell] = 1;
           have_inv = true;
         } else {

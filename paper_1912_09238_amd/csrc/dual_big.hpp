@@ -253,14 +253,14 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
     const bool stale = reuse && chord && have_inv;  // uniform
     double d = 0.0;
     double H[T][T];
-    double* Hc = reuse ? P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) *
+    float* Hc = reuse ? P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) *
                                       P.hinv_stride
                        : nullptr;
     if (stale) {
 #pragma unroll
       for (int i = 0; i < T; ++i)
 #pragma unroll
-        for (int j = 0; j < T; ++j) H[i][j] = Hc[(i * T + j) * 256 + tid];
+        for (int j = 0; j < T; ++j) H[i][j] = static_cast<double>(Hc[(i * T + j) * 256 + tid]);
       d = inverse_times(H, g);
     } else {
     // ---- Hessian tiles
@@ -412,7 +412,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 #pragma unroll
       for (int i = 0; i < T; ++i)
 #pragma unroll
-        for (int j = 0; j < T; ++j) Hc[(i * T + j) * 256 + tid] = H[i][j];
+        for (int j = 0; j < T; ++j) Hc[(i * T + j) * 256 + tid] = static_cast<float>(H[i][j]);
       if (tid == 0) P.hinv_ok[cell] = 1;
       have_inv = true;
       d = inverse_times(H, g);

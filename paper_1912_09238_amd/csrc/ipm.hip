@@ -50,7 +50,7 @@ struct DualClass {
   int* d_order = nullptr;   // [count] cells of the class ascending (null: all cells)
   int blk_off = 0, blk_cnt = 0;  // range in the block-statistics array
   bool merged = false;      // its cells go to the lists of a larger class
-  double* d_hinv = nullptr; // inexact-Hessian Newton: stored inverses of the class's cells
+  float* d_hinv = nullptr;  // inexact-Hessian Newton: stored inverses of the class's cells (FP32)
   int n_min = 0, n_max = 0; // unknowns of the cells its launches solve (set-up)
   // register-row inexact-Hessian classes: chord steps in a kernel of their
   // own, then the full kernel over the cells it handed on
@@ -105,7 +105,7 @@ struct Problem {
   int* d_hinv_slot = nullptr;          // [cells] slot within the class's inverses
   // with adaptive levels: one slot per cell of the largest class's size (a
   // cell moves between classes; a level change retires its inverse)
-  double* d_hinv_all = nullptr;
+  float* d_hinv_all = nullptr;
   long long hinv_all_stride = 0;
   // the class's inverses and their size (set per launch)
   void set_hinv(DualParams& d, const DualClass& D) const {
@@ -410,10 +410,12 @@ void free_problem(Problem* P) {
 
 // Phi columns a class's Newton kernel stages in LDS: those its rows read
 // (the lane groups' padded rows for register rows; 16 T / m for the tiles),
-// at most the global table's
+// at most the global table's.  Register rows read a node's row per lane, so
+// their stride is made odd (conflict-free banks; the kernel zero-fills a
+// column beyond the global table).
 int class_kl(int M, int kp, int NP, int T) {
-  const int k = T > 0 ? (16 * T + M - 1) / M : dual_table_columns(M, NP);
-  return std::min(kp, k);
+  if (T > 0) return std::min(kp, (16 * T + M - 1) / M);
+  return std::min(kp, dual_table_columns(M, NP)) | 1;
 }
 
 // shape key of a small-kernel class for the autotuner
@@ -462,15 +464,14 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   // many quadrature nodes would not fit LDS
   auto upd_lds_for = [&](int waves) {
     const size_t cpb = static_cast<size_t>(waves) * (64 / P.UG);
-    return sizeof(double) * (static_cast<size_t>(P.Q) * P.kp + 2 * cpb * P.Q * P.M + 256 +
+    return sizeof(double) * (2 * cpb * P.Q * P.M + 256 +
                              (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
   };
   P.upd_waves = 4;
   while (P.upd_waves > 1 && upd_lds_for(P.upd_waves) > ctx->max_lds) P.upd_waves >>= 1;
   const int ucpb = P.upd_waves * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
-  P.upd_lds = sizeof(double) * (static_cast<size_t>(P.Q) * P.kp +
-                                2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
+  P.upd_lds = sizeof(double) * (2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
                                 (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
   if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
   P.dual_blocks = 0;
@@ -1333,14 +1334,14 @@ static size_t reuse_bytes(const ipm_problem* pb, int M, size_t cells) {
   if (pb->adapt) {  // one slot per cell of the largest class's size
     const int k = size_class(M * binom_basis(pb->p, pb->degree));
     const size_t np = k >= 4 ? 16 * class_tiles(k) : std::max(16, 8 << k);
-    return b + cells * np * np * sizeof(double);
+    return b + cells * np * np * sizeof(float);
   }
   for (size_t c = 0; c < cells; ++c) {
     const int dg = pb->cell_degree ? pb->cell_degree[c] : pb->degree;
     const int n = M * binom_basis(pb->p, dg);
     const int k = size_class(n);
     const size_t np = k >= 4 ? 16 * class_tiles(k) : std::max(16, 8 << k);
-    b += sizeof(double) * np * np;
+    b += sizeof(float) * np * np;
   }
   return b;
 }
@@ -1574,7 +1575,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
       if (D.configured && (D.prec & 2)) npmax = std::max(npmax, D.NP);
     if (npmax > 0) {
       P.hinv_all_stride = static_cast<long long>(npmax) * npmax;
-      ALLOC(P.d_hinv_all, static_cast<size_t>(P.cells) * P.hinv_all_stride * sizeof(double));
+      ALLOC(P.d_hinv_all, static_cast<size_t>(P.cells) * P.hinv_all_stride * sizeof(float));
       ALLOC(P.d_hinv_ok, static_cast<size_t>(P.cells));
     }
   } else if (P.hessian_reuse) {
@@ -1582,7 +1583,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     bool any = false;
     for (DualClass& D : P.cls)
       if (D.configured && (D.prec & 2) && D.order_len > 0) {
-        ALLOC(D.d_hinv, static_cast<size_t>(D.order_len) * D.NP * D.NP * sizeof(double));
+        ALLOC(D.d_hinv, static_cast<size_t>(D.order_len) * D.NP * D.NP * sizeof(float));
         any = true;
       }
     if (any) {

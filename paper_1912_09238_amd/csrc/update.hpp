@@ -152,12 +152,13 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
   step_slots(C, P.parity, P.dim, slot_x, slot_y);
   extern __shared__ double smem[];
   const int Q = P.Q, kp = P.kp, N = P.N;
-  double* wphiL = smem;
-  for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) wphiL[k] = P.wphi[k];
+  // the weighted basis table is read from device memory (cached): kept out
+  // of LDS, so that more wavefronts fit a CU
+  const double* __restrict__ wphiL = P.wphi;
   constexpr int CPW = 64 / G;
   const int groups = (blockDim.x >> 6) * CPW;
   const bool analytic = M == 1 && P.flux == kFluxSgAnalytic;
-  double* ctpL = wphiL + Q * kp;                         // analytic flux: [N][N][N]
+  double* ctpL = smem;                                   // analytic flux: [N][N][N]
   if (analytic)
     for (int k = threadIdx.x; k < N * N * N; k += blockDim.x) ctpL[k] = P.ctp[k];
   double* UT = ctpL + (analytic ? N * N * N : 0);         // per group [Q][M] updated nodes
@@ -227,8 +228,16 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         l[b] = first ? pw[b] : uw[q * M + b];
         rr[b] = first ? pe[b] : ue[q * M + b];
       }
-      numerical_flux<M>(analytic ? kFluxLF : P.flux, P.gamma, 0, c, rr, lfx, gr);
-      numerical_flux<M>(analytic ? kFluxLF : P.flux, P.gamma, 0, l, c, lfx, gl);
+      // each state's division and square root once (the cell's own state
+      // enters four face fluxes and its wave speeds)
+      const FluxState<M> sc = flux_state<M>(P.gamma, c);
+      const int kind = analytic ? kFluxLF : P.flux;
+      {
+        const FluxState<M> sr = flux_state<M>(P.gamma, rr);
+        const FluxState<M> sl = flux_state<M>(P.gamma, l);
+        numerical_flux_s<M>(kind, 0, c, sc, rr, sr, lfx, gr);
+        numerical_flux_s<M>(kind, 0, l, sl, c, sc, lfx, gl);
+      }
 #pragma unroll
       for (int b = 0; b < M; ++b) acc[b] = c[b] - rx * (gr[b] - gl[b]);
       if (P.dim == 2) {
@@ -237,8 +246,10 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
           l[b] = first ? ps[b] : us[q * M + b];
           rr[b] = first ? pn[b] : un[q * M + b];
         }
-        numerical_flux<M>(P.flux, P.gamma, 1, c, rr, lfy, gr);
-        numerical_flux<M>(P.flux, P.gamma, 1, l, c, lfy, gl);
+        const FluxState<M> sr = flux_state<M>(P.gamma, rr);
+        const FluxState<M> sl = flux_state<M>(P.gamma, l);
+        numerical_flux_s<M>(P.flux, 1, c, sc, rr, sr, lfy, gr);
+        numerical_flux_s<M>(P.flux, 1, l, sl, c, sc, lfy, gl);
 #pragma unroll
         for (int b = 0; b < M; ++b) acc[b] -= ry * (gr[b] - gl[b]);
       }
@@ -248,8 +259,9 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         uq[q * M + b] = c[b];
       }
       if (!P.one_shot) {
-        double sx, sy;
-        wave_speeds<M>(P.gamma, P.dim, c, sx, sy);
+        double f[M], sx, sy = 0.0;
+        state_flux<M>(sc, 0, c, f, sx);
+        if (P.dim == 2) state_flux<M>(sc, 1, c, f, sy);
         nx_speed = nan_max(nx_speed, sx);
         ny_speed = nan_max(ny_speed, sy);
       }

@@ -7,7 +7,7 @@ deterministic sample of cells.
   t_end = 0.14 (Alg. 1), FP64 form.
 - 2D bump, 512 x 512 cells, degree 5, 8 x 8 nodes: 2 time steps in the FP64
   form, and in the mixed-precision form (BF16 Hessian on the matrix cores +
-  inexact-Hessian Newton with stored FP64 inverses, FP64 tau test).
+  inexact-Hessian Newton with stored FP32 inverses, FP64 tau test).
 - The 64-problem batch (three uncertainties, per-cell degrees 1-4, 5^3
   nodes), all problems stepped together: 2 time steps, FP64 and mixed
   precision, every problem checked.
