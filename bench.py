@@ -78,12 +78,15 @@ MIXED = dict(precision="bf16", hessian_reuse=2)
 PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
 
 
-def class_flops(n, m, Q, listed, iterations, fresh, c_closure=80):
+def class_flops(n, m, Q, listed, iterations, fresh, c_closure=80, evaluations=0):
     """Algorithmic FP64-equivalent flops of a size class's Newton work
     (symmetric minimum): each solved cell evaluates the ansatz and the
     gradient once on entry; an iteration with a fresh Hessian adds the
     assembly, the Cholesky solve and the re-evaluation; an iteration with a
-    stored inverse adds its matrix-vector product and the re-evaluation."""
+    stored inverse adds its matrix-vector product and the re-evaluation.
+    Where the kernel counts its passes over the nodes (evaluations: entry
+    and every line-search trial), those replace the one re-evaluation per
+    iteration."""
     N = n // m
     f_eval = 2 * m * N * Q + Q * c_closure
     f_grad = 2 * m * N * Q + m * N
@@ -91,6 +94,8 @@ def class_flops(n, m, Q, listed, iterations, fresh, c_closure=80):
     f_chol = n ** 3 / 3 + 2 * n * n + n
     f_eg = f_eval + f_grad
     stale = iterations - fresh
+    if evaluations:
+        return evaluations * f_eg + fresh * (f_hess + f_chol) + stale * 2 * n * n
     return listed * f_eg + fresh * (f_hess + f_chol + f_eg) + stale * (2 * n * n + f_eg)
 
 
@@ -256,10 +261,11 @@ def _class_totals(ctx, ids):
         for c in ctx.class_stats(pid):
             key = (c["workgroup"], c["lanes"], c["variant"])
             t = tot.setdefault(key, {"n_min": c["n_min"], "n_max": c["n_max"], "cells": 0,
-                                     "listed": 0, "iterations": 0, "fresh": 0})
+                                     "listed": 0, "iterations": 0, "fresh": 0,
+                                     "evaluations": 0})
             t["n_min"] = min(t["n_min"], c["n_min"])
             t["n_max"] = max(t["n_max"], c["n_max"])
-            for k in ("cells", "listed", "iterations", "fresh"):
+            for k in ("cells", "listed", "iterations", "fresh", "evaluations"):
                 t[k] += c[k]
     return tot
 
@@ -303,10 +309,11 @@ def timed_batch(ctx, specs, nodes, extra, warmup, steps, m=4, Q=125):
     for t in lt:
         key = (t["workgroup"], t["lanes"], t["variant"])
         c = c1[key]
-        d = {k: c[k] - c0[key][k] for k in ("listed", "iterations", "fresh")}
+        d = {k: c[k] - c0[key][k] for k in ("listed", "iterations", "fresh", "evaluations")}
         assert c["n_min"] == c["n_max"], ("one size per class", key, c)
         n = c["n_max"]
-        flops = class_flops(n, m, Q, d["listed"], d["iterations"], d["fresh"])
+        flops = class_flops(n, m, Q, d["listed"], d["iterations"], d["fresh"],
+                            evaluations=d["evaluations"])
         nbytes = class_bytes(n, m, Q, d["listed"], d["iterations"], d["fresh"], key[2])
         avg = t["ms"] / t["launches"] * 1e-3
         kernels.append({"kernel": _kernel_name(m, key), "unknowns": n,
@@ -315,6 +322,8 @@ def timed_batch(ctx, specs, nodes, extra, warmup, steps, m=4, Q=125):
                         "listed_per_launch": d["listed"] / t["launches"],
                         "iterations_per_listed": d["iterations"] / max(1, d["listed"]),
                         "fresh_per_listed": d["fresh"] / max(1, d["listed"]),
+                        "evaluations_per_iteration":
+                            d["evaluations"] / max(1, d["iterations"]) if d["evaluations"] else None,
                         "flops_per_launch": flops / t["launches"],
                         "bytes_per_launch": nbytes / t["launches"],
                         "achieved_tflops": flops / t["launches"] / avg / 1e12,

@@ -157,7 +157,9 @@ typedef struct {
      64 for n <= 64 and to a multiple of 16 above: 4 KB per cell at n = 30,
      about 37 KB at n = 84) and takes later
      Newton steps, in this and following time steps, as d = H_old^-1 grad L
-     while each such step contracts the dual residual by reuse_theta;
+     (on fixed degrees with the L-BFGS correction of the cell's last accepted
+     step of the same time step) while each such step contracts the dual
+     residual by reuse_theta;
      otherwise the inverse is retired and the next iteration (one-shot: of
      the next pseudo-time step) assembles and inverts afresh.  The tau test is
      unchanged, so the dual still converges to tau; results agree with exact
@@ -367,8 +369,12 @@ ipm_status ipm_launch_times(ipm_ctx *ctx, ipm_launch_time *out, int cap, int *n)
    the range of unknowns n = m N of the cells they solve, the class's cells,
    and how many cells the launches solved (listed), their Newton iterations
    (eq:dualIterationFunction steps) and how many of these assembled a fresh
-   Hessian (the rest reused a stored inverse).  *n = classes reported (at
-   most cap are written).  Measurement helper. */
+   Hessian (the rest reused a stored inverse).  Classes with a chord kernel
+   (inexact-Hessian Newton on fixed degrees) report it as a second entry
+   with variant 10, whose evaluations counts its passes over the quadrature
+   nodes (the ansatz and gradient at the entry point and at every line-search
+   trial; 0 in the other entries).  *n = classes reported (at most cap are
+   written).  Measurement helper. */
 typedef struct {
   int size_class;
   int workgroup;  /* as in ipm_launch_time */
@@ -379,6 +385,7 @@ typedef struct {
   long long listed;
   long long iterations;
   long long fresh;
+  long long evaluations;
 } ipm_class_stat;
 ipm_status ipm_class_stats(ipm_ctx *ctx, int id, ipm_class_stat *out, int cap, int *n);
 

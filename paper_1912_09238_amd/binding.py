@@ -78,7 +78,8 @@ class ClassStat(C.Structure):
     _fields_ = [("size_class", C.c_int), ("workgroup", C.c_int), ("lanes", C.c_int),
                 ("variant", C.c_int), ("n_min", C.c_int), ("n_max", C.c_int),
                 ("cells", C.c_longlong), ("listed", C.c_longlong),
-                ("iterations", C.c_longlong), ("fresh", C.c_longlong)]
+                ("iterations", C.c_longlong), ("fresh", C.c_longlong),
+                ("evaluations", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

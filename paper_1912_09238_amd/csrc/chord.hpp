@@ -25,6 +25,11 @@
 
 namespace ipm {
 
+// Secant pairs kept per cell within a launch: the step applies the stored
+// inverse with the L-BFGS two-loop corrections of the cell's last accepted
+// steps (0: plain chord steps).
+constexpr int kChordPairs = 1;
+
 template <int M, int NP>
 struct ChordCfg {
   static constexpr int G = NP;
@@ -47,6 +52,14 @@ struct ChordCfg {
                              2 * static_cast<size_t>(waves) * (CPW + 1));
   }
 };
+
+// A cell's counters in one double (exact below 2^53): iterations (10 bits),
+// passes over the nodes (30 bits), listed flag.
+__device__ __forceinline__ double pack_stats(int its, int evals, bool listed) {
+  return static_cast<double>(static_cast<unsigned long long>(its) |
+                             (static_cast<unsigned long long>(evals) << 10) |
+                             (listed ? (1ull << 40) : 0ull));
+}
 
 // Hand a cell on to the full kernel: marked (hinv_ok = 2, no valid inverse)
 // and appended to its class's list for this step.
@@ -96,7 +109,9 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   if (!__syncthreads_or(cell >= 0)) return;
 
   const int Q = P.Q, kg = P.kp, kp = P.kl, N = P.N;
-  const int Nc = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) : 0;
+  // one cell per wavefront: its size is wave-uniform (scalar loop control)
+  int Nc = cell >= 0 ? (P.cellN ? static_cast<int>(P.cellN[cell]) : N) : 0;
+  if (CPW == 1) Nc = __builtin_amdgcn_readfirstlane(Nc);
   const int nc = Nc * M;
   const int ii = r / M, aa = r % M;
   const bool live = r < nc;
@@ -121,7 +136,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   double* stats = areas + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
   __syncthreads();
 
-  int its = 0;
+  int its = 0, evals = 0;  // evals: passes over the nodes (entry and each trial)
   unsigned status = 0;
   bool pending = false;
   double sx = 0.0, sy = 0.0;
@@ -136,6 +151,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     // of this lane's unknown, node by node in ascending order
     double ssum = 0.0, gacc = 0.0;
     auto grad_pass = [&]() -> int {
+      ++evals;
       int okp = 1;
       ssum = 0.0;
       gacc = 0.0;
@@ -172,6 +188,13 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     double res = 0.0;
     if (ok) res = gradient();
     else status |= kStRealizability;
+    // secant pairs s = lambda_k+1 - lambda_k, y = g_k+1 - g_k of this launch,
+    // oldest first in the last npair slots, with rho = 1 / (y . s)
+    constexpr int KP = kChordPairs > 0 ? kChordPairs : 1;
+    double sp[KP], yp[KP], rho[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) sp[k] = yp[k] = rho[k] = 0.0;
+    int npair = 0;
     while (ok) {
       if (!(res == res) || res > 1e300) {
         status |= kStNonfinite;
@@ -184,23 +207,46 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
           break;
         }
       }
-      // ---- d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area
-      lamS[r] = g;
-      wave_sync();
-      // the stored entries of 16 columns requested at once (unconditional
-      // loads: a column past nc re-reads the last one and is not summed),
-      // then summed in ascending column order
-      double acc = 0.0;
-      if (live)
-        for (int c0 = 0; c0 < nc; c0 += 16) {
-          float h[16];
+      // ---- d = H^-1 g = -(rows of -H^-1) g, g through the group's LDS area;
+      // with secant pairs, the two-loop recursion around the stored inverse
+      double qv = g, alpha[KP];
+      if (kChordPairs > 0) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j) h[j] = Hc[min(c0 + j, nc - 1) * nc + r];
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (c0 + j < nc) acc = fma(static_cast<double>(h[j]), lamS[c0 + j], acc);
+        for (int k = KP - 1; k >= 0; --k) {
+          alpha[k] = 0.0;
+          if (k >= KP - npair) {  // uniform
+            alpha[k] = rho[k] * group_sum<G>(sp[k] * qv);
+            qv = fma(-alpha[k], yp[k], qv);
+          }
         }
-      const double d = live ? -acc : 0.0;
+      }
+      lamS[r] = qv;
+      wave_sync();
+      // the stored entries of B columns requested at once, then summed in
+      // ascending column order.  Loads are unconditional: a column past nc
+      // re-reads the last one, and its product with the zero that lamS holds
+      // there (g = 0 beyond nc, B divides NP) adds nothing.
+      constexpr int B = NP < 16 ? NP : 16;
+      double acc = 0.0;
+      if (live) {
+        const global_fptr hp = Hc + r;
+        for (int c0 = 0; c0 < nc; c0 += B) {
+          float h[B];
+#pragma unroll
+          for (int j = 0; j < B; ++j) h[j] = hp[min(c0 + j, nc - 1) * nc];
+#pragma unroll
+          for (int j = 0; j < B; ++j) acc = fma(static_cast<double>(h[j]), lamS[c0 + j], acc);
+        }
+      }
+      double d = live ? -acc : 0.0;
+      if (kChordPairs > 0) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+          if (k >= KP - npair) {  // uniform
+            const double beta = rho[k] * group_sum<G>(yp[k] * d);
+            d = fma(sp[k], alpha[k] - beta, d);
+          }
+      }
       wave_sync();
       // ---- step length (as the full kernel: backtracking while far from tau)
       const bool ls = !P.one_shot && res > 1e-6;
@@ -234,6 +280,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
         status |= kStLineSearch;
         break;
       }
+      const double lam_old = lam, g_old = g;
       lam = lt;
       ++its;
       if (!ok) {
@@ -242,6 +289,22 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       }
       const double res_old = res;
       res = gradient();
+      if (kChordPairs > 0) {
+        const double s_new = lam - lam_old, y_new = g - g_old;
+        const double ys = group_sum<G>(s_new * y_new);
+        if (ys > 0.0) {  // strictly convex L: always, up to rounding
+#pragma unroll
+          for (int k = 0; k + 1 < KP; ++k) {
+            sp[k] = sp[k + 1];
+            yp[k] = yp[k + 1];
+            rho[k] = rho[k + 1];
+          }
+          sp[KP - 1] = s_new;
+          yp[KP - 1] = y_new;
+          rho[KP - 1] = 1.0 / ys;
+          npair = npair < KP ? npair + 1 : KP;
+        }
+      }
       // no contraction by theta: the inverse is retired; the cell goes on in
       // the full kernel (its next iteration assembles afresh), or, one-shot,
       // at its next pseudo-time step
@@ -278,7 +341,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   sx = wave_max(sx);
   sy = wave_max(sy);
   if (r == 0) {
-    stats[(wave * CPW + grp) * 2 + 0] = static_cast<double>(its + (cell >= 0 ? 1048576 : 0));
+    stats[(wave * CPW + grp) * 2 + 0] = pack_stats(its, evals, cell >= 0);
     stats[(wave * CPW + grp) * 2 + 1] = static_cast<double>(status);
   }
   if (lane == 0) {
@@ -287,7 +350,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long sum_its = 0, max_its = 0, listed = 0;
+    unsigned long long sum_its = 0, max_its = 0, listed = 0, sum_evals = 0;
     unsigned st = 0;
     double mx = 0.0, my = 0.0;
     for (int k = 0; k < waves * CPW; ++k) {
@@ -295,7 +358,8 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       const unsigned long long it = v & 1023ull;
       sum_its += it;
       max_its = it > max_its ? it : max_its;
-      listed += v >> 20;
+      sum_evals += (v >> 10) & 0x3fffffffull;
+      listed += v >> 40;
       st |= static_cast<unsigned>(stats[2 * k + 1]);
     }
     for (int w = 0; w < waves; ++w) {
@@ -307,6 +371,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     bs[0] += sum_its;
     if (max_its > bs[1]) bs[1] = max_its;
     bs[2] += listed;
+    bs[3] += sum_evals;
     if (st) atomicOr(&P.ctrl->status, st);
     atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
     if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));

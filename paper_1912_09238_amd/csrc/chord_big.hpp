@@ -9,8 +9,11 @@
 // tile owner), and every sum is formed as there: per-thread partial sums,
 // each wavefront-sum over the same 64 threads, the four combined as
 // (w0 + w1) + (w2 + w3); the product with the stored tiles per tile row,
-// then over the 16 column threads in ascending order.  The results are
-// those of the workgroup kernel bit for bit.  A cell without a valid
+// then over the 16 column threads in ascending order.  After its first step
+// a cell's steps add the L-BFGS correction of its last accepted step (one
+// secant pair) around the stored inverse, which the workgroup kernel does
+// not; the pass over the nodes and the stored product are the workgroup
+// kernel's bit for bit.  A cell without a valid
 // inverse, or whose step fails to contract the dual residual by theta, is
 // handed on (hinv_ok = 2) to the workgroup kernel in pending mode.
 #pragma once
@@ -20,12 +23,17 @@
 
 namespace ipm {
 
+// Secant pairs kept per cell within a launch (0 or 1): the step applies the
+// stored inverse with the L-BFGS correction of the cell's last accepted step.
+constexpr int kChordBigPairs = 1;
+
 template <int M, int T>
 struct ChordBigCfg {
   static constexpr int NPB = 16 * T;
   static constexpr int NJ = M * (M + 1) / 2;
-  // per cell: dual [NPB], ansatz [Q][M], gradient [NPB], step [NPB]
-  __host__ __device__ static int cell_doubles(int Q) { return 3 * NPB + Q * M; }
+  // per cell: dual [NPB], ansatz [Q][M], gradient [NPB], step [NPB], and the
+  // secant pair s, y [2][NPB]
+  __host__ __device__ static int cell_doubles(int Q) { return 5 * NPB + Q * M; }
   // node stride of the table, stored mode by mode (odd: lanes of different
   // modes read different banks)
   __host__ __device__ static int qstride(int Q) { return Q | 1; }
@@ -71,10 +79,12 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
   double* US = lamS + NPB;   // [Q][M]
   double* gS = US + Q * M;   // [NPB]
   double* dS = gS + NPB;     // [NPB]
-  double* stats = dS + NPB;  // [4]: its + listed, status, speeds x, y
+  double* sP = dS + NPB;     // [NPB] secant pair: s = lambda_k+1 - lambda_k
+  double* yP = sP + NPB;     // [NPB]                y = g_k+1 - g_k
+  double* stats = yP + NPB;  // [4]: its + listed, status, speeds x, y
   __syncthreads();
 
-  int its = 0;
+  int its = 0, evals = 0;  // evals: passes over the nodes (entry and each trial)
   unsigned status = 0;
   bool pending = false;
   double sx = 0.0, sy = 0.0;
@@ -103,6 +113,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     double ssum[4];
     // the ansatz at node v of each stand-in thread: U to LDS, <s_*> shares
     auto eval = [&]() -> int {
+      ++evals;
       int okp = 1;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -143,6 +154,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     double res = 0.0;
     if (ok) res = gradient();
     else status |= kStRealizability;
+    double rho1 = 0.0, alpha = 0.0;  // 1 / (y . s) of the pair; its first-loop coefficient
+    bool pair = false;               // uniform
     while (ok) {
       if (!(res == res) || res > 1e300) {
         status |= kStNonfinite;
@@ -158,10 +171,21 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       // ---- d = H^-1 g from the stored tiles: tile thread u = 64 s + lane
       // (rows tr + 16 i, columns tc + 16 j) forms its row sums, the 16
       // column threads of a row are then added in ascending order
+      // with a secant pair, the stored inverse acts on q = g - alpha y,
+      // alpha = rho s . g (the two-loop recursion with one pair)
+      if (kChordBigPairs > 0 && pair) {
+        double x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int v = lane + 64 * s;
+          x[s] = (live[s] && v < NPB) ? sP[v] * g[s] : 0.0;
+        }
+        alpha = rho1 * wg_sum4(x);
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int v = lane + 64 * s;
-        if (v < NPB) gS[v] = live[s] ? g[s] : 0.0;
+        if (v < NPB) gS[v] = live[s] ? (pair ? fma(-alpha, yP[v], g[s]) : g[s]) : 0.0;
       }
       wave_sync();
       const int tc = lane & 15;
@@ -205,6 +229,20 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         d[s] = (live[s] && v < NPB) ? dS[v] : 0.0;
       }
       wave_sync();
+      if (kChordBigPairs > 0 && pair) {  // second loop: d += s (alpha - rho y . d)
+        double x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int v = lane + 64 * s;
+          x[s] = (live[s] && v < NPB) ? yP[v] * d[s] : 0.0;
+        }
+        const double beta = rho1 * wg_sum4(x);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int v = lane + 64 * s;
+          if (live[s] && v < NPB) d[s] = fma(sP[v], alpha - beta, d[s]);
+        }
+      }
       // ---- step length
       const bool ls = !P.one_shot && res > 1e-6;
       double L0 = 0.0, slope = 0.0;
@@ -249,6 +287,16 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         status |= kStLineSearch;
         break;
       }
+      if (kChordBigPairs > 0) {  // the new pair (each lane its own entries)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int v = lane + 64 * s;
+          if (v < NPB) {
+            sP[v] = live[s] ? lt[s] - lam[s] : 0.0;
+            yP[v] = live[s] ? -g[s] : 0.0;
+          }
+        }
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) lam[s] = lt[s];
       ++its;
@@ -258,6 +306,22 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       }
       const double res_old = res;
       res = gradient();
+      if (kChordBigPairs > 0) {
+        double x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int v = lane + 64 * s;
+          x[s] = 0.0;
+          if (v < NPB) {
+            const double y = live[s] ? yP[v] + g[s] : 0.0;
+            yP[v] = y;
+            x[s] = sP[v] * y;
+          }
+        }
+        const double ys = wg_sum4(x);
+        pair = ys > 0.0;  // strictly convex L: always, up to rounding
+        rho1 = pair ? 1.0 / ys : 0.0;
+      }
       if (!(res <= P.reuse_theta * res_old)) {
         if (P.one_shot) {
           if (lane == 0) P.hinv_ok[cell] = 0;
@@ -293,14 +357,14 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
   sx = wave_max(sx);
   sy = wave_max(sy);
   if (lane == 0) {
-    stats[0] = static_cast<double>(its + (cell >= 0 ? 1048576 : 0));
+    stats[0] = pack_stats(its, evals, cell >= 0);
     stats[1] = static_cast<double>(status);
     stats[2] = sx;
     stats[3] = sy;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long sum_its = 0, max_its = 0, listed = 0;
+    unsigned long long sum_its = 0, max_its = 0, listed = 0, sum_evals = 0;
     unsigned st = 0;
     double mx = 0.0, my = 0.0;
     for (int w = 0; w < waves; ++w) {
@@ -309,7 +373,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       const unsigned long long it = v & 1023ull;
       sum_its += it;
       max_its = it > max_its ? it : max_its;
-      listed += v >> 20;
+      sum_evals += (v >> 10) & 0x3fffffffull;
+      listed += v >> 40;
       st |= static_cast<unsigned>(o[1]);
       mx = nan_max(mx, o[2]);
       my = nan_max(my, o[3]);
@@ -319,20 +384,28 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     bs[0] += sum_its;
     if (max_its > bs[1]) bs[1] = max_its;
     bs[2] += listed;
+    bs[3] += sum_evals;
     if (st) atomicOr(&P.ctrl->status, st);
     atomicMax(&P.ctrl->amax[P.parity][0][slot], speed_bits(mx));
     if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));
   }
 }
 
+// three wavefronts per SIMD (168 registers) where LDS allows three
+// workgroups per CU (up to T = 6 at 125 nodes); no request above (their LDS
+// allows two, and a two-wave cap cost the 144-row class 9 % of its time)
+template <int T>
+constexpr int chord_big_waves() { return T <= 6 ? 3 : 1; }
+
 template <int M, int T>
-__global__ __launch_bounds__(256) void newton_chord_big_kernel(DualParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(chord_big_waves<T>())))
+void newton_chord_big_kernel(DualParams P) {
   chord_big_body<M, T>(P, blockIdx.x);
 }
 
 template <int M, int T>
-__global__ __launch_bounds__(256) void newton_chord_big_batched(const DualParams* __restrict__ PP,
-                                                                const int* __restrict__ begin, int n) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(chord_big_waves<T>())))
+void newton_chord_big_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
   chord_big_body<M, T>(PP[k], blockIdx.x - begin[k]);
 }

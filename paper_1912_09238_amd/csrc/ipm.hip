@@ -2338,6 +2338,7 @@ ipm_status ipm_class_stats(ipm_ctx* ctx, int id, ipm_class_stat* out, int cap, i
       for (int b = D.cblk_off; b < D.cblk_off + D.cblk_cnt; ++b) {
         t.iterations += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b)]);
         t.listed += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b) + 2]);
+        t.evaluations += static_cast<long long>(blk[kBlkStats * static_cast<size_t>(b) + 3]);
       }
       if (k < cap) out[k] = t;
       ++k;
