@@ -100,13 +100,16 @@ def class_flops(n, m, Q, listed, iterations, fresh, c_closure=80, evaluations=0)
 
 
 def class_bytes(n, m, Q, listed, iterations, fresh, variant):
-    """Algorithmic HBM bytes of a size class's Newton work: per solved cell
-    the dual and the moments read, the dual and the nodal ansatz written;
-    with stored inverses (variant bit 1) each step from a stored inverse
-    reads its n x n FP32 entries and each fresh one writes them."""
+    """Algorithmic HBM bytes of a size class's Newton work (each byte once,
+    the Newton loop on chip): per solved cell the dual and the moments read,
+    the dual and the nodal ansatz written; with stored inverses (variant
+    bit 1, and the chord kernels, variant 10) the cell's n x n FP32 inverse
+    read once, and written once per fresh Hessian.  Re-reads of the inverse
+    by later steps of the same launch are the implementation's (served
+    from L2 when the active cells' inverses fit there), not the method's."""
     b = listed * (3 * n + Q * m) * 8
     if variant & 2:
-        b += iterations * n * n * 4
+        b += (listed + fresh) * n * n * 4
     return b
 
 
@@ -273,6 +276,8 @@ def _class_totals(ctx, ids):
 def _kernel_name(m, key):
     workgroup, lanes, variant = key
     if variant == 10:
+        if workgroup:
+            return "newton_chord_big_batched<%d,%d>" % (m, lanes // 16)
         return "newton_chord_batched<%d,%d>" % (m, lanes)
     if workgroup:
         return "newton_big_batched<%d,%d,%d>" % (m, lanes // 16, variant)
