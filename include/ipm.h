@@ -76,8 +76,10 @@ enum { IPM_ENT_QUADRATIC = 0, IPM_ENT_LOG_BARRIER = 1, IPM_ENT_EULER = 2 };
    the rule integrates degree 3M exactly. */
 enum { IPM_FLUX_LF = 0, IPM_FLUX_RUSANOV = 1, IPM_FLUX_SG_ANALYTIC = 2 };
 enum { IPM_BC_OUTFLOW = 0, IPM_BC_PERIODIC = 1, IPM_BC_DIRICHLET = 2 };
-/* arithmetic of the Hessian assembly (Newton update, Cholesky solve, gradient
-   and the tau test are always FP64).  IPM_PREC_BF16: split-BF16 products on
+/* arithmetic of the Hessian assembly (the Newton update, the SPD solve --
+   Gauss-Jordan elimination without pivoting, n^3 flops against Cholesky's
+   n^3/3, chosen for its broadcast-only data flow on register rows --, the
+   gradient and the tau test are always FP64).  IPM_PREC_BF16: split-BF16 products on
    the matrix cores for cells of 65..96 unknowns; smaller cells (register-row
    kernels) and larger ones (whose FP32 block area would cost occupancy)
    keep the FP64 assembly.  IPM_PREC_FP32 is rejected (no faster than FP64

@@ -184,10 +184,23 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(aa == b ? g * g : 0.0));
       return res;
     };
-    int ok = group_all(grad_pass());
+    // the previous update's warm start (Euler entropy): the gradient and
+    // <s_*> at this dual, which spares the entry pass over the nodes
+    const bool warm = P.gwarm != nullptr && P.ctrl->gwarm[P.parity] != 0;  // uniform
+    bool entry_warm = warm;
+    double s0 = 0.0;
+    int ok = 1;
     double res = 0.0;
-    if (ok) res = gradient();
-    else status |= kStRealizability;
+    if (warm) {
+      g = live ? P.gwarm[gidx] : 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(aa == b ? g * g : 0.0));
+      s0 = P.s0[cell];
+    } else {
+      ok = group_all(grad_pass());
+      if (ok) res = gradient();
+      else status |= kStRealizability;
+    }
     // secant pairs s = lambda_k+1 - lambda_k, y = g_k+1 - g_k of this launch,
     // oldest first in the last npair slots, with rho = 1 / (y . s)
     constexpr int KP = kChordPairs > 0 ? kChordPairs : 1;
@@ -252,9 +265,10 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       const bool ls = !P.one_shot && res > 1e-6;
       double L0 = 0.0, slope = 0.0;
       if (ls) {
-        L0 = group_sum<G>(ssum - lam * uh);
+        L0 = entry_warm ? s0 - group_sum<G>(lam * uh) : group_sum<G>(ssum - lam * uh);
         slope = group_sum<G>(g * d);
       }
+      entry_warm = false;  // from here on ssum is the accepted trial's
       double t = 1.0, lt = lam;
       int accepted = 0;
 #pragma unroll 1

@@ -150,10 +150,29 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       for (int b = 0; b < M; ++b) res += sqrt(wg_sum4(e2[b]));
       return res;
     };
-    int ok = eval();
+    // the previous update's warm start (Euler entropy): the gradient and
+    // <s_*> at this dual, which spares the entry pass over the nodes
+    const bool warm = P.gwarm != nullptr && P.ctrl->gwarm[P.parity] != 0;  // uniform
+    bool entry_warm = warm;
+    double s0 = 0.0;
+    int ok = 1;
     double res = 0.0;
-    if (ok) res = gradient();
-    else status |= kStRealizability;
+    if (warm) {
+      double e2[M][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        g[s] = live[s] ? P.gwarm[gidx[s]] : 0.0;
+#pragma unroll
+        for (int b = 0; b < M; ++b) e2[b][s] = (live[s] && ra[s] == b) ? g[s] * g[s] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < M; ++b) res += sqrt(wg_sum4(e2[b]));
+      s0 = P.s0[cell];
+    } else {
+      ok = eval();
+      if (ok) res = gradient();
+      else status |= kStRealizability;
+    }
     double rho1 = 0.0, alpha = 0.0;  // 1 / (y . s) of the pair; its first-loop coefficient
     bool pair = false;               // uniform
     while (ok) {
@@ -250,12 +269,14 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         double x0[4], x1[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          x0[s] = ssum[s] - (live[s] ? lam[s] * uh[s] : 0.0);
+          x0[s] = (entry_warm ? 0.0 : ssum[s]) - (live[s] ? lam[s] * uh[s] : 0.0);
           x1[s] = live[s] ? g[s] * d[s] : 0.0;
         }
         L0 = wg_sum4(x0);
+        if (entry_warm) L0 += s0;
         slope = wg_sum4(x1);
       }
+      entry_warm = false;  // from here on ssum is the accepted trial's
       double t = 1.0, lt[4];
       int accepted = 0;
 #pragma unroll 1
@@ -339,6 +360,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     if (pending || status) {
       if (lane == 0 && pending) hand_on(P, cell);
     } else {
+      if (evals == 0) (void)eval();  // converged at the warm start: the ansatz once
       for (int q = lane; q < Q; q += 64) {
         double u[M];
 #pragma unroll

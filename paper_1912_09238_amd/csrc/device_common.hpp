@@ -21,7 +21,7 @@ enum : unsigned {
   kStNewton = 1u,
   kStRealizability = 2u,
   kStNonfinite = 4u,
-  kStCholesky = 8u,
+  kStPivot = 8u,  // a non-positive pivot in the SPD elimination
   kStLineSearch = 16u,
 };
 

@@ -78,6 +78,9 @@ struct StepCtrl {
   unsigned int list_len[2 * kCls * kSlots * kSlotStride];
   // [parity][class] cells the chord kernels handed on to the full kernel
   unsigned int pend_len[2][kCls];
+  // [parity] 1: the update before the step of this parity left the warm-start
+  // gradient and <s_*> of every cell (the chord kernels start from them)
+  int gwarm[2];
 };
 
 __host__ __device__ inline size_t list_len_index(int parity, int cls, int slot) {
@@ -100,6 +103,11 @@ struct DualParams {
   int* __restrict__ pend_list;      // [class cells] cells handed on (chord kernels append)
   const int8_t* __restrict__ cellN; // modes per cell, or null (all N)
   const double* __restrict__ uhat;  // [cells][M][N]
+  // warm start left by the previous update (chord kernels; null: none):
+  // the dual gradient at the cell's current dual [cells][M][N] and the
+  // quadrature sum of s_* there [cells], valid when ctrl->gwarm[parity]
+  const double* __restrict__ gwarm;
+  const double* __restrict__ s0;
   double* __restrict__ lam;         // [cells][M][N], in/out
   double* __restrict__ nodal;       // [cells][Q][M], out
   // [gridDim.x][kBlkStats]: Newton iterations, their max over the block's
@@ -684,7 +692,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
             });
           }
           if (!group_all(pd_ok)) {
-            status |= kStCholesky;
+            status |= kStPivot;
             break;
           }
 #pragma unroll
@@ -738,7 +746,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
               __builtin_amdgcn_sched_barrier(0);
             });
             if (!group_all(pd_ok)) {
-              status |= kStCholesky;
+              status |= kStPivot;
               break;
             }
             x[0] = xv;
@@ -790,7 +798,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
               }
             }
             if (!group_all(pd_ok)) {
-              status |= kStCholesky;
+              status |= kStPivot;
               break;
             }
             wave_sync();

@@ -406,7 +406,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
         }
       }
       if (!pd_ok) {  // uniform: every thread read the same pivots
-        status |= kStCholesky;
+        status |= kStPivot;
         break;
       }
 #pragma unroll
@@ -459,7 +459,7 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
       }
     }
     if (!pd_ok) {  // uniform: every thread read the same pivots
-      status |= kStCholesky;
+      status |= kStPivot;
       break;
     }
     d = row_live ? x * recip(dg) : 0.0;

@@ -93,6 +93,11 @@ struct Problem {
   double* d_nodal = nullptr;
   double* d_ghost = nullptr;
   double* d_res = nullptr;
+  // chord kernels on the Euler entropy: the update leaves each cell's
+  // warm-start dual gradient (in the old moments' buffer) and <s_*> [cells]
+  bool gwarm = false;
+  double* d_s0 = nullptr;
+  bool upd_stage = false;  // the update stages its basis table in LDS
   unsigned long long* d_blk = nullptr;
   // modes per cell read by the steps of each parity (one buffer when fixed;
   // adaptive: the update of a step writes the other parity's buffer)
@@ -396,7 +401,8 @@ Problem* get(ipm_ctx* ctx, int id) {
 void free_problem(Problem* P) {
   if (!P) return;
   void* ptrs[] = {P->d_phi,   P->d_wphi, P->d_u[0], P->d_u[1],  P->d_lam, P->d_nodal,
-                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv_ok, P->d_hinv_slot, P->d_hinv_all};
+                  P->d_ghost, P->d_res,  P->d_blk,  P->d_cellN[0], P->d_ctrl, P->d_retard, P->d_ctp, P->d_hinv_ok, P->d_hinv_slot, P->d_hinv_all,
+                  P->d_s0};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->d_cellN[1] && P->d_cellN[1] != P->d_cellN[0]) (void)hipFree(P->d_cellN[1]);
@@ -462,16 +468,20 @@ ipm_status plan(ipm_ctx* ctx, Problem& P, const int* counts) {
   P.UG = pow2_at_least(std::min(64, std::max(P.Q, n)), 16);
   // update blocks of 4 wavefronts, or fewer when the per-cell node tiles of
   // many quadrature nodes would not fit LDS
+  // the weighted basis table goes to LDS up to 16 KiB (short latency for the
+  // small, latency-bound problems), else it is read from device memory
+  P.upd_stage = static_cast<size_t>(P.Q) * P.kp * sizeof(double) <= 16384;
+  const size_t tab = P.upd_stage ? static_cast<size_t>(P.Q) * P.kp : 0;
   auto upd_lds_for = [&](int waves) {
     const size_t cpb = static_cast<size_t>(waves) * (64 / P.UG);
-    return sizeof(double) * (2 * cpb * P.Q * P.M + 256 +
+    return sizeof(double) * (tab + 2 * cpb * P.Q * P.M + 256 +
                              (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
   };
   P.upd_waves = 4;
   while (P.upd_waves > 1 && upd_lds_for(P.upd_waves) > ctx->max_lds) P.upd_waves >>= 1;
   const int ucpb = P.upd_waves * (64 / P.UG);
   P.upd_blocks = (P.cells + ucpb - 1) / ucpb;
-  P.upd_lds = sizeof(double) * (2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
+  P.upd_lds = sizeof(double) * (tab + 2 * static_cast<size_t>(ucpb) * P.Q * P.M + 256 +
                                 (P.flux == IPM_FLUX_SG_ANALYTIC ? static_cast<size_t>(P.N) * P.N * P.N : 0));
   if (P.upd_lds > ctx->max_lds) return fail(ctx, IPM_E_ARG, "quadrature too large for the update kernel");
   P.dual_blocks = 0;
@@ -613,6 +623,11 @@ DualParams dual_params(const Problem& P, int mode, int parity, const double* uha
   d.dim = P.dim;
   d.ctrl = ctrl;
   d.parity = parity;
+  // the other moments buffer holds the warm start the last update left
+  if (mode == 0 && P.gwarm && uhat == P.d_u[parity]) {
+    d.gwarm = P.d_u[parity ^ 1];
+    d.s0 = P.d_s0;
+  }
   return d;
 }
 
@@ -711,6 +726,9 @@ UpdateParams update_params(const Problem& P, int parity) {
   u.ghost = P.d_ghost;
   u.uold = P.d_u[parity];
   u.unew = P.d_u[parity ^ 1];
+  u.gwarm = P.gwarm ? 1 : 0;
+  u.stage_table = P.upd_stage ? 1 : 0;
+  u.s0 = P.d_s0;
   u.res_part = P.d_res;
   for (int k = 0; k < 4; ++k) u.bc[k] = P.bc[k];
   u.flux = P.flux;
@@ -1264,6 +1282,24 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
 
 }  // namespace
 
+// Device temporaries of one call: freed when the call returns, on every
+// path, once the stream has drained.
+struct TempBuffers {
+  hipStream_t s;
+  std::vector<void*> p;
+  template <class T>
+  hipError_t alloc(T** ptr, size_t bytes) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), bytes);
+    if (e == hipSuccess) p.push_back(static_cast<void*>(*ptr));
+    return e;
+  }
+  ~TempBuffers() {
+    if (p.empty()) return;
+    (void)hipStreamSynchronize(s);
+    for (void* x : p) (void)hipFree(x);
+  }
+};
+
 extern "C" {
 
 const char* ipm_last_error(const ipm_ctx* ctx) {
@@ -1565,6 +1601,10 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     if (P.uneven && D.order_len > 0) ALLOC(D.d_order, static_cast<size_t>(D.order_len) * sizeof(int));
   }
   ALLOC(P.d_ctrl, sizeof(StepCtrl));
+  P.gwarm = false;
+  if (P.cp.entropy == kEntEuler && !P.adapt)
+    for (const DualClass& D : P.cls) P.gwarm = P.gwarm || D.chord;
+  if (P.gwarm) ALLOC(P.d_s0, static_cast<size_t>(P.cells) * sizeof(double));
   if (pb->n_retard > 0) ALLOC(P.d_retard, sizeof(Retard));
   if (P.flux == IPM_FLUX_SG_ANALYTIC)
     ALLOC(P.d_ctp, static_cast<size_t>(P.N) * P.N * P.N * sizeof(double));
@@ -1685,15 +1725,17 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   CHK(hipMemsetAsync(P.d_ghost, 0, 4 * static_cast<size_t>(P.Q) * P.M * sizeof(double), s));
   CHK(hipMemsetAsync(P.d_nodal, 0, nod * sizeof(double), s));
 
-  // staging of the host inputs
+  // staging of the host inputs (freed on every return, after the stream
+  // has drained)
+  TempBuffers staging{s, {}};
   double* d_in = nullptr;
   double* d_dual = nullptr;
   const size_t in_len = pb->ic_nodal ? nod : cn;
-  CHK(hipMalloc(&d_in, in_len * sizeof(double)));
+  CHK(staging.alloc(&d_in, in_len * sizeof(double)));
   CHK(hipMemcpyAsync(d_in, pb->ic_nodal ? pb->ic_nodal : pb->ic_moments, in_len * sizeof(double),
                      hipMemcpyHostToDevice, s));
   if (pb->ic_dual) {
-    CHK(hipMalloc(&d_dual, cn * sizeof(double)));
+    CHK(staging.alloc(&d_dual, cn * sizeof(double)));
     CHK(hipMemcpyAsync(d_dual, pb->ic_dual, cn * sizeof(double), hipMemcpyHostToDevice, s));
   }
   SetupParams sp{};
@@ -1733,16 +1775,17 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     std::vector<double> gin(nd * gq);
     for (int k = 0; k < nd; ++k)
       std::memcpy(&gin[k * gq], pb->dirichlet + dsides[k] * gq, gq * sizeof(double));
+    TempBuffers gtemps{s, {}};  // the ghosts' temporaries, freed on every return
     double *d_gin = nullptr, *d_gu = nullptr, *d_gl = nullptr, *d_gn = nullptr;
     StepCtrl* d_gc = nullptr;
     unsigned long long* d_gb = nullptr;
-    CHK(hipMalloc(&d_gb, 64 * sizeof(unsigned long long)));
+    CHK(gtemps.alloc(&d_gb, 64 * sizeof(unsigned long long)));
     CHK(hipMemsetAsync(d_gb, 0, 64 * sizeof(unsigned long long), s));
-    CHK(hipMalloc(&d_gin, gin.size() * sizeof(double)));
-    CHK(hipMalloc(&d_gu, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
-    CHK(hipMalloc(&d_gl, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
-    CHK(hipMalloc(&d_gn, gin.size() * sizeof(double)));
-    CHK(hipMalloc(&d_gc, sizeof(StepCtrl)));
+    CHK(gtemps.alloc(&d_gin, gin.size() * sizeof(double)));
+    CHK(gtemps.alloc(&d_gu, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
+    CHK(gtemps.alloc(&d_gl, nd * static_cast<size_t>(P.M) * P.N * sizeof(double)));
+    CHK(gtemps.alloc(&d_gn, gin.size() * sizeof(double)));
+    CHK(gtemps.alloc(&d_gc, sizeof(StepCtrl)));
     CHK(hipMemsetAsync(d_gc, 0, sizeof(StepCtrl), s));
     CHK(hipMemcpyAsync(d_gin, gin.data(), gin.size() * sizeof(double), hipMemcpyHostToDevice, s));
     SetupParams gp = sp;
@@ -1765,12 +1808,6 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
     StepCtrl gc;
     CHK(hipMemcpyAsync(&gc, d_gc, sizeof(StepCtrl), hipMemcpyDeviceToHost, s));
     CHK(hipStreamSynchronize(s));
-    (void)hipFree(d_gin);
-    (void)hipFree(d_gu);
-    (void)hipFree(d_gl);
-    (void)hipFree(d_gn);
-    (void)hipFree(d_gc);
-    (void)hipFree(d_gb);
     if (gc.setup_status || gc.status)
       return cleanup(fail(ctx, IPM_E_REALIZABILITY, "Dirichlet ghost state has no admissible dual"));
     for (int k = 0; k < kSlots; ++k) {
@@ -1781,8 +1818,6 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   StepCtrl hc;
   CHK(hipMemcpyAsync(&hc, P.d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, s));
   CHK(hipStreamSynchronize(s));
-  if (d_in) (void)hipFree(d_in);
-  if (d_dual) (void)hipFree(d_dual);
   if (hc.setup_status) {
     std::string why = (hc.setup_status & kStRealizability) ? "initial state outside the entropy's domain"
                       : (hc.setup_status & kStNewton)      ? "initial dual did not converge"
@@ -1798,6 +1833,10 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   CHK(hipStreamSynchronize(s));
 #undef CHK
   P.charged = std::max(fp, P.bytes);
+  // the estimate admitted the problem; the allocation it made is what counts
+  if (ctx->budget && ctx->used + P.charged > ctx->budget)
+    return cleanup(fail(ctx, IPM_E_NOMEM, "problem does not fit the HBM budget (allocated " +
+                                              std::to_string(P.bytes) + " bytes)"));
   ctx->used += P.charged;
   ++ctx->gen;
   ctx->problems[slot] = std::move(up);

@@ -48,7 +48,12 @@ struct UpdateParams {
   const int8_t* __restrict__ cellN;
   const double* __restrict__ nodal;  // [cells][Q][M]
   const double* __restrict__ ghost;  // [4][Q][M] Dirichlet ghost nodal states
-  const double* __restrict__ uold;   // [cells][M][N]
+  // [cells][M][N] the step's old moments; with gwarm, overwritten by the
+  // next step's warm-start dual gradient once read
+  double* __restrict__ uold;
+  double* __restrict__ s0;           // [cells] next step's <s_*> at the warm start (gwarm), else null
+  int gwarm;                         // 1: leave the warm start for the chord kernels (Euler entropy)
+  int stage_table;                   // 1: the weighted basis table is staged in LDS (small tables)
   double* __restrict__ unew;         // [cells][M][N]
   double* __restrict__ res_part;     // [gridDim.x]
   int bc[4];
@@ -152,13 +157,19 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
   step_slots(C, P.parity, P.dim, slot_x, slot_y);
   extern __shared__ double smem[];
   const int Q = P.Q, kp = P.kp, N = P.N;
-  // the weighted basis table is read from device memory (cached): kept out
-  // of LDS, so that more wavefronts fit a CU
+  // the weighted basis table: staged in LDS when small, else read from
+  // device memory (cached), which leaves the LDS to more wavefronts per CU
   const double* __restrict__ wphiL = P.wphi;
+  double* tail = smem;
+  if (P.stage_table) {
+    for (int k = threadIdx.x; k < Q * kp; k += blockDim.x) smem[k] = P.wphi[k];
+    wphiL = smem;
+    tail = smem + Q * kp;
+  }
   constexpr int CPW = 64 / G;
   const int groups = (blockDim.x >> 6) * CPW;
   const bool analytic = M == 1 && P.flux == kFluxSgAnalytic;
-  double* ctpL = smem;                                   // analytic flux: [N][N][N]
+  double* ctpL = tail;                                   // analytic flux: [N][N][N]
   if (analytic)
     for (int k = threadIdx.x; k < N * N * N; k += blockDim.x) ctpL[k] = P.ctp[k];
   double* UT = ctpL + (analytic ? N * N * N : 0);         // per group [Q][M] updated nodes
@@ -412,7 +423,11 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
             P.unew[off] = v[b];
             const double g = h[b] - v[b];  // next step's dual gradient at its warm start
             gsq[b] = fma(g, g, gsq[b]);
+            if (P.gwarm) P.uold[off] = g;
           }
+          // Euler entropy: s_*(lambda . phi) = (gamma - 1) rho, so its
+          // quadrature sum is (gamma - 1) times mode 0 of the density's h
+          if (P.gwarm && i == 0) P.s0[cell] = (P.gamma - 1.0) * h[0];
         }
       }
       // modes above the level: zero (a lowered cell's old moments there
@@ -495,6 +510,7 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         }
       }
     if (blk == 0 && k == 0) {
+      C->gwarm[P.parity ^ 1] = P.gwarm;
       C->t[P.parity ^ 1] = last ? P.t_end : t0 + dt;
       C->done[P.parity ^ 1] = last ? 1 : 0;
       C->dt_last = dt;
