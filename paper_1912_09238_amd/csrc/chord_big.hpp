@@ -111,7 +111,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         (global_fptr)(P.hinv + static_cast<size_t>(P.hinv_slot ? P.hinv_slot[cell] : cell) * P.hinv_stride);
     wave_sync();
     double ssum[4];
-    // the ansatz at node v of each stand-in thread: U to LDS, <s_*> shares
+    // the ansatz at node v of each stand-in thread: w_q u_s to LDS (the
+    // product the gradient sum takes, formed once per node), <s_*> shares
     auto eval = [&]() -> int {
       ++evals;
       int okp = 1;
@@ -123,7 +124,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
           double u[M], ss;
           okp &= node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss) ? 1 : 0;
 #pragma unroll
-          for (int a = 0; a < M; ++a) US[q * M + a] = u[a];
+          for (int a = 0; a < M; ++a) US[q * M + a] = u[a] * wL[q];
           ssum[s] = fma(wL[q], ss, ssum[s]);
         }
       }
@@ -138,7 +139,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
         double gg = 0.0;
         if (live[s]) {
           const double* pr = phiT + ri[s] * QT;
-          for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra[s]] * wL[q], pr[q], gg);
+          for (int q = 0; q < Q; ++q) gg = fma(US[q * M + ra[s]], pr[q], gg);
           gg -= uh[s];
         }
         g[s] = gg;
@@ -360,11 +361,10 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     if (pending || status) {
       if (lane == 0 && pending) hand_on(P, cell);
     } else {
-      if (evals == 0) (void)eval();  // converged at the warm start: the ansatz once
+      // the ansatz of the final dual (staged in lamS), node by node
       for (int q = lane; q < Q; q += 64) {
-        double u[M];
-#pragma unroll
-        for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+        double u[M], ss;
+        (void)node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss);
 #pragma unroll
         for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
         double ax, ay;

@@ -29,6 +29,7 @@ struct ClosureParams {
   int entropy;
   double gamma, um, up;
   double log_range;  // ln(u_plus - u_minus), log-barrier constant of s_*
+  double r1mg;       // 1 / (1 - gamma): the Euler closure multiplies by it
 };
 
 // Orders LDS traffic between the lanes of one wavefront (no s_barrier).
@@ -105,7 +106,7 @@ __device__ __forceinline__ bool closure(const ClosureParams& cp, const double* L
       v[k] = L[1 + k] * ib;
       vv += v[k] * v[k];
     }
-    const double lnrho = (log(beta) - 0.5 * beta * vv + cp.gamma - L[0]) / (1.0 - cp.gamma);
+    const double lnrho = (log(beta) - 0.5 * beta * vv + cp.gamma - L[0]) * cp.r1mg;
     const double rho = exp(lnrho);
     const double h = 0.5 * vv + ib;
     u[0] = rho;

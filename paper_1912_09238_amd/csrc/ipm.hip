@@ -1366,7 +1366,8 @@ ipm_status ipm_basis_table(int p, int degree, int quad_per_dim, double* Phi, int
 // (NP = 16T for the workgroup kernel; at least 16 for small cells, which
 // may run on it), plus flags/slots
 static size_t reuse_bytes(const ipm_problem* pb, int M, size_t cells) {
-  size_t b = cells * (1 + sizeof(int));
+  // valid flags and slots; the chord kernels' warm-start <s_*> (Euler)
+  size_t b = cells * (1 + sizeof(int)) + (pb->entropy == IPM_ENT_EULER ? cells * sizeof(double) : 0);
   if (pb->adapt) {  // one slot per cell of the largest class's size
     const int k = size_class(M * binom_basis(pb->p, pb->degree));
     const size_t np = k >= 4 ? 16 * class_tiles(k) : std::max(16, 8 << k);
@@ -1488,6 +1489,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.vol = P.dim == 2 ? P.dx * P.dy : P.dx;
   P.cp.entropy = pb->entropy;
   P.cp.gamma = pb->gamma;
+  P.cp.r1mg = 1.0 / (1.0 - pb->gamma);
   P.cp.um = pb->u_minus;
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
