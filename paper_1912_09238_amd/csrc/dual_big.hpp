@@ -565,12 +565,14 @@ __device__ __forceinline__ void newton_big_body(const DualParams& P, const int b
 }
 
 // PREC bit 0: BF16-split MFMA Hessian; bit 1: inexact-Hessian Newton.
-// Two workgroups per CU for the BF16 variants up to T = 6, with or without
-// inverse reuse (their per-cell latency is the lower one, so the launch is
-// occupancy bound; uncapped, the MFMA accumulators push the register count
-// just past two wavefronts' share); larger tiles do not fit
+// Two workgroups per CU up to T = 6 in every variant (the launch is
+// occupancy bound; uncapped, the MFMA accumulators of the BF16 variants,
+// and at T = 6 the FP64 variants' pending-mode and counter state, push the
+// register count just past two wavefronts' share: the FP64 T = 6 kernel
+// took 259 registers, one wavefront per SIMD, and ran the 2D bump at 0.57x);
+// larger tiles do not fit
 template <int M, int T, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T <= 6 ? 2 : 1)))
 void newton_big_kernel(DualParams P) {
   if (P.pend) {  // after the chord kernel: the handed-on cells
     const int n = static_cast<int>(P.ctrl->pend_len[P.parity][P.cls]);
@@ -584,7 +586,7 @@ void newton_big_kernel(DualParams P) {
 }
 
 template <int M, int T, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 1) && T <= 6) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T <= 6 ? 2 : 1)))
 void newton_big_batched(const DualParams* __restrict__ PP,
                                                           const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);

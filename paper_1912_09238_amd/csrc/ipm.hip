@@ -991,6 +991,12 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
 
 // Build a batch plan in device buffers of its own: upload the parameter
 // arrays and instantiate one graph per parity.
+ipm_status add_graphs(ipm_ctx* ctx, BatchPlan& Bp);
+
+// A batch plan: its launches and their parameter arrays on the device.  The
+// graphs are added when the same plan is stepped a second time (add_graphs):
+// a plan that changes every call (a serving loop admitting and finishing
+// requests) runs launch by launch instead of paying two instantiations.
 ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out) {
   auto B = std::make_unique<BatchPlan>();
   std::vector<DualParams> dps;
@@ -1009,6 +1015,12 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
                              hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(ctx, hipMalloc(&B->d_dev_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  out = std::move(B);
+  return IPM_OK;
+}
+
+ipm_status add_graphs(ipm_ctx* ctx, BatchPlan& Bp) {
+  BatchPlan* B = &Bp;
   // one graph per parity: Newton launches in parallel, then the updates,
   // then the steady residuals
   for (int ph = 0; ph < 2; ++ph) {
@@ -1072,7 +1084,6 @@ ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_pt
     }
     HIPCHK(ctx, hipGraphInstantiate(&B->exec[ph], B->graph[ph], nullptr, nullptr, 0));
   }
-  out = std::move(B);
   return IPM_OK;
 }
 
@@ -1140,8 +1151,11 @@ ipm_status launch_batch_step(ipm_ctx* ctx, const BatchPlan& B, int ph, hipEvent_
 ipm_status run_batch(ipm_ctx* ctx, BatchPlan& B, int steps) {
   for (int s = 0; s < steps; ++s) {
     const int ph = static_cast<int>(B.steps_done & 1);
-    if (!ctx->timing) {
+    if (!ctx->timing && B.exec[ph]) {
       HIPCHK(ctx, hipGraphLaunch(B.exec[ph], ctx->stream));
+    } else if (!ctx->timing) {
+      ipm_status st = launch_batch_step(ctx, B, ph, nullptr);
+      if (st != IPM_OK) return st;
     } else {
       while (ctx->ev.size() < ctx->ev_used + 4) {
         hipEvent_t e;
@@ -1281,6 +1295,24 @@ ipm_status validate(ipm_ctx* ctx, const ipm_problem* pb) {
 }
 
 }  // namespace
+
+// The scalar fields at the head of a problem's control block (time, stop
+// flags, status, step and Newton counters): what the host reads between
+// steps, without the speed slots and list lengths behind them (96 KB).
+constexpr size_t kCtrlHead = offsetof(StepCtrl, amax);
+
+// The first fields of the control block alone (the serving loop's poll).
+struct CtrlFlags {
+  double t[2];
+  int done[2];
+  unsigned int status;
+  unsigned int setup_status;
+  unsigned long long steps;
+};
+static_assert(offsetof(CtrlFlags, done) == offsetof(StepCtrl, done) &&
+                  offsetof(CtrlFlags, status) == offsetof(StepCtrl, status) &&
+                  offsetof(CtrlFlags, steps) == offsetof(StepCtrl, steps),
+              "CtrlFlags mirrors the head of StepCtrl");
 
 // Device temporaries of one call: freed when the call returns, on every
 // path, once the stream has drained.
@@ -1873,6 +1905,9 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
       ctx->batch.reset();
       ipm_status st = build_batch(ctx, v, ctx->batch);
       if (st != IPM_OK) return st;
+    } else if (!ctx->batch->exec[0]) {
+      ipm_status st = add_graphs(ctx, *ctx->batch);  // the plan is stepped again: replay it
+      if (st != IPM_OK) return st;
     }
     ipm_status st = run_batch(ctx, *ctx->batch, max_steps);
     if (st != IPM_OK) return st;
@@ -1978,7 +2013,7 @@ ipm_status ipm_query(ipm_ctx* ctx, int id, ipm_step_info* info) {
   if (!P) return fail(ctx, IPM_E_STATE, "ipm_query: unknown problem id");
   if (!info) return fail(ctx, IPM_E_ARG, "ipm_query: info is NULL");
   StepCtrl hc;
-  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, kCtrlHead, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   info->done = (hc.done[hc.steps & 1] || hc.status) ? 1 : 0;
   info->steps = static_cast<long long>(hc.steps);
@@ -2010,7 +2045,7 @@ ipm_status ipm_moments(ipm_ctx* ctx, int id, double* out, size_t out_len, int ou
   const size_t cn = static_cast<size_t>(P->cells) * P->M * P->N;
   if (!out || out_len < cn) return fail(ctx, IPM_E_ARG, "ipm_moments: output too small");
   StepCtrl hc;
-  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, kCtrlHead, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   const double* src = P->d_u[hc.steps & 1];
   HIPCHK(ctx, hipMemcpyAsync(out, src, cn * sizeof(double),
@@ -2043,7 +2078,7 @@ ipm_status ipm_cell_degrees(ipm_ctx* ctx, int id, int8_t* out, size_t out_len) {
     return IPM_OK;
   }
   StepCtrl hc;
-  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, sizeof(StepCtrl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(&hc, P->d_ctrl, kCtrlHead, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   std::vector<int8_t> modes(P->cells);
   HIPCHK(ctx, hipMemcpyAsync(modes.data(), P->d_cellN[hc.steps & 1], modes.size(),
@@ -2099,7 +2134,7 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
   size_t next = 0;
   int finished = 0;
   std::vector<int> active_req, active_id;
-  std::vector<StepCtrl> ctrl;
+  std::vector<CtrlFlags> ctrl;
   while (finished < n) {
     // admission, in arrival order, while slots and HBM budget allow
     while (next < order.size() && reqs[order[next]].arrival_s <= now_s() &&
@@ -2133,11 +2168,11 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
     if (st != IPM_OK) return st;
     ctrl.resize(active_id.size());
     for (size_t k = 0; k < active_id.size(); ++k)
-      HIPCHK(ctx, hipMemcpyAsync(&ctrl[k], get(ctx, active_id[k])->d_ctrl, sizeof(StepCtrl),
+      HIPCHK(ctx, hipMemcpyAsync(&ctrl[k], get(ctx, active_id[k])->d_ctrl, sizeof(CtrlFlags),
                                  hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     for (size_t k = 0; k < active_id.size();) {
-      const StepCtrl& hc = ctrl[k];
+      const CtrlFlags& hc = ctrl[k];
       const bool done = hc.done[hc.steps & 1] || hc.status;
       if (!done) {
         ++k;
