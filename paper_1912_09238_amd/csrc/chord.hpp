@@ -53,6 +53,30 @@ struct ChordCfg {
   }
 };
 
+// Sum over the lanes of each residue class mod 4 within aligned groups of G
+// = 16, 32 or 64 lanes (rotations by 4 and 8 inside each 16-lane row, then
+// exchanges across rows): every lane receives its class's total.
+template <int G>
+__device__ __forceinline__ double class4_sum(double v) {
+  v += dpp_mov<0x124>(v);  // row_ror:4
+  v += dpp_mov<0x128>(v);  // row_ror:8
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// The residual of the tau test, sum over the m = 4 variables of the
+// Euclidean norm of the gradient over the modes, for a group whose lane r
+// holds unknown (i, a) with a = r mod 4: one class sum and one square root
+// per lane, the four norms then added within each quad (the same value in
+// every lane: addition commutes).
+template <int G>
+__device__ __forceinline__ double tau_residual4(double g) {
+  const double s = sqrt(class4_sum<G>(g * g));
+  const double t = s + dpp_mov<0xB1>(s);
+  return t + dpp_mov<0x4E>(t);
+}
+
 // A cell's counters in one double (exact below 2^53): iterations (10 bits),
 // passes over the nodes (30 bits), listed flag.
 __device__ __forceinline__ double pack_stats(int its, int evals, bool listed) {
@@ -177,12 +201,16 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
       return okp;
     };
     double g = 0.0;
-    auto gradient = [&]() -> double {
-      g = live ? gacc - uh : 0.0;
+    auto norm = [&]() -> double {
+      if constexpr (M == 4 && G >= 16) return tau_residual4<G>(g);
       double res = 0.0;
 #pragma unroll
       for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(aa == b ? g * g : 0.0));
       return res;
+    };
+    auto gradient = [&]() -> double {
+      g = live ? gacc - uh : 0.0;
+      return norm();
     };
     // the previous update's warm start (Euler entropy): the gradient and
     // <s_*> at this dual, which spares the entry pass over the nodes
@@ -193,8 +221,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     double res = 0.0;
     if (warm) {
       g = live ? P.gwarm[gidx] : 0.0;
-#pragma unroll
-      for (int b = 0; b < M; ++b) res += sqrt(group_sum<G>(aa == b ? g * g : 0.0));
+      res = norm();
       s0 = P.s0[cell];
     } else {
       ok = group_all(grad_pass());
