@@ -71,10 +71,14 @@ __device__ __forceinline__ double class4_sum(double v) {
 // per lane, the four norms then added within each quad (the same value in
 // every lane: addition commutes).
 template <int G>
-__device__ __forceinline__ double tau_residual4(double g) {
-  const double s = sqrt(class4_sum<G>(g * g));
+__device__ __forceinline__ double tau_residual4_sq(double g2) {
+  const double s = sqrt(class4_sum<G>(g2));
   const double t = s + dpp_mov<0xB1>(s);
   return t + dpp_mov<0x4E>(t);
+}
+template <int G>
+__device__ __forceinline__ double tau_residual4(double g) {
+  return tau_residual4_sq<G>(g * g);
 }
 
 // A cell's counters in one double (exact below 2^53): iterations (10 bits),

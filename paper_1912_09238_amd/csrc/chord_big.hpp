@@ -9,11 +9,11 @@
 // tile owner), and every sum is formed as there: per-thread partial sums,
 // each wavefront-sum over the same 64 threads, the four combined as
 // (w0 + w1) + (w2 + w3); the product with the stored tiles per tile row,
-// then over the 16 column threads in ascending order.  After its first step
-// a cell's steps add the L-BFGS correction of its last accepted step (one
-// secant pair) around the stored inverse, which the workgroup kernel does
-// not; the pass over the nodes and the stored product are the workgroup
-// kernel's bit for bit.  A cell without a valid
+// then over the 16 column threads in ascending order.  The pass over the
+// nodes and the stored product are the workgroup kernel's bit for bit; the
+// scalar sums of the step (residual, line search, the L-BFGS correction of
+// the cell's last accepted step, which the workgroup kernel does not take)
+// add a lane's four slots first and take one wavefront sum.  A cell without a valid
 // inverse, or whose step fails to contract the dual residual by theta, is
 // handed on (hinv_ok = 2) to the workgroup kernel in pending mode.
 #pragma once
@@ -46,8 +46,9 @@ struct ChordBigCfg {
 };
 
 // sum over the workgroup kernel's 256 threads, thread 64 s + lane in slot s
-__device__ __forceinline__ double wg_sum4(const double (&x)[4]) {
-  return (wave_sum(x[0]) + wave_sum(x[1])) + (wave_sum(x[2]) + wave_sum(x[3]));
+// (the four slots of a lane first: one wavefront sum instead of four)
+__device__ __forceinline__ double sum4(const double (&x)[4]) {
+  return wave_sum((x[0] + x[1]) + (x[2] + x[3]));
 }
 
 template <int M, int T>
@@ -132,6 +133,23 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       return __ballot(!okp) == 0ull ? 1 : 0;
     };
     double g[4];
+    // the tau residual from the squared gradient entries by variable; with
+    // four variables every slot of a lane holds the same variable (64 s +
+    // lane = lane mod 4), so one class sum over the lanes serves
+    auto residual = [&](const double (&e2)[M][4]) -> double {
+      if constexpr (M == 4) {
+        double e = 0.0;  // the other variables' entries of a lane are zero
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int b = 0; b < M; ++b) e += e2[b][s];
+        return tau_residual4_sq<64>(e);
+      }
+      double res = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) res += sqrt(sum4(e2[b]));
+      return res;
+    };
     auto gradient = [&]() -> double {
       double e2[M][4];
 #pragma unroll
@@ -146,10 +164,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
 #pragma unroll
         for (int b = 0; b < M; ++b) e2[b][s] = (live[s] && ra[s] == b) ? gg * gg : 0.0;
       }
-      double res = 0.0;
-#pragma unroll
-      for (int b = 0; b < M; ++b) res += sqrt(wg_sum4(e2[b]));
-      return res;
+      return residual(e2);
     };
     // the previous update's warm start (Euler entropy): the gradient and
     // <s_*> at this dual, which spares the entry pass over the nodes
@@ -166,8 +181,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
 #pragma unroll
         for (int b = 0; b < M; ++b) e2[b][s] = (live[s] && ra[s] == b) ? g[s] * g[s] : 0.0;
       }
-#pragma unroll
-      for (int b = 0; b < M; ++b) res += sqrt(wg_sum4(e2[b]));
+      res = residual(e2);
       s0 = P.s0[cell];
     } else {
       ok = eval();
@@ -200,7 +214,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
           const int v = lane + 64 * s;
           x[s] = (live[s] && v < NPB) ? sP[v] * g[s] : 0.0;
         }
-        alpha = rho1 * wg_sum4(x);
+        alpha = rho1 * sum4(x);
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -256,7 +270,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
           const int v = lane + 64 * s;
           x[s] = (live[s] && v < NPB) ? yP[v] * d[s] : 0.0;
         }
-        const double beta = rho1 * wg_sum4(x);
+        const double beta = rho1 * sum4(x);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int v = lane + 64 * s;
@@ -273,9 +287,9 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
           x0[s] = (entry_warm ? 0.0 : ssum[s]) - (live[s] ? lam[s] * uh[s] : 0.0);
           x1[s] = live[s] ? g[s] * d[s] : 0.0;
         }
-        L0 = wg_sum4(x0);
+        L0 = sum4(x0);
         if (entry_warm) L0 += s0;
-        slope = wg_sum4(x1);
+        slope = sum4(x1);
       }
       entry_warm = false;  // from here on ssum is the accepted trial's
       double t = 1.0, lt[4];
@@ -298,7 +312,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
           double x[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s) x[s] = ssum[s] - (live[s] ? lt[s] * uh[s] : 0.0);
-          if (wg_sum4(x) <= L0 - 1e-4 * t * slope) {
+          if (sum4(x) <= L0 - 1e-4 * t * slope) {
             accepted = 1;
             break;
           }
@@ -340,7 +354,7 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
             x[s] = sP[v] * y;
           }
         }
-        const double ys = wg_sum4(x);
+        const double ys = sum4(x);
         pair = ys > 0.0;  // strictly convex L: always, up to rounding
         rho1 = pair ? 1.0 / ys : 0.0;
       }
