@@ -265,9 +265,11 @@ ipm_status ipm_step(ipm_ctx *ctx, int n_ids, const int *ids, int max_steps,
    parameter arrays and block offsets live in a fixed device array of
    512 KiB per GPU (defined in the library, held until the process ends),
    not in allocations of the call; ids whose arrays would exceed it (per
-   problem and step parity 240 bytes per Newton size class plus 368 for the
-   update: about 2.7 KB for a problem with four classes, so about 190 such
-   problems) fail with IPM_E_ARG and a message naming the size.  The problems' own state comes from ipm_set_problem as for
+   problem and step parity 272 bytes per Newton launch -- one per size
+   class, two for a class with a chord kernel -- plus 384 for the update and
+   8 bytes of block offsets per launch: about 5.3 KB over both parities for
+   a problem with four chord classes, so about 99 such problems) fail with
+   IPM_E_ARG and a message naming the size.  The problems' own state comes from ipm_set_problem as for
    ipm_step.  Every call on a GPU shares that GPU's array, which keeps the
    last call's contents: the first call for an id list (or after another
    list, context or ipm_step has used the array or moved the problems)
