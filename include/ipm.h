@@ -361,7 +361,8 @@ typedef struct {
   int m;          /* conserved variables of the kernel */
   int lanes;      /* register-row kernel: lanes per cell; workgroup kernel: 16 T rows */
   int workgroup;  /* 1: one workgroup per cell (T x T register tiles), 0: register rows */
-  int variant;    /* bit 0: BF16 MFMA Hessian; bit 1: stored inverse Hessians */
+  int variant;    /* bit 0: BF16 MFMA Hessian; bit 1: stored inverse Hessians;
+                     bit 2: register rows holding all nodes at once (Q <= lanes) */
   int threads;    /* threads per block */
   long long launches;
   double ms;

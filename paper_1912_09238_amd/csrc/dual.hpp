@@ -35,7 +35,10 @@
 //        such step contracts the dual residual by a factor theta; otherwise
 //        the inverse is retired and the next iteration (one-shot: of the
 //        next pseudo-time step) assembles and inverts afresh.  The tau test
-//        is unchanged.
+//        is unchanged;
+//      - single-chunk variant (PREC bit 2): for rules of at most NP nodes,
+//        which a cell's lanes hold in one chunk; the streaming code is
+//        compiled out (fewer registers, a plain node loop).
 // The dual, the nodal ansatz (read by the flux update) and the wave speeds
 // leave the kernels; the exact variant's Hessian never touches HBM.
 // Statistics go to per-block cumulative counters (plain stores) and to 64
@@ -444,7 +447,9 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
   const int gidx_l = wave * CPW + grp;
   double* lamS = wphiL + Q * kp + static_cast<size_t>(gidx_l) * Cfg::group_doubles(Q);  // [NP]
   const int CH = Cfg::chunk(Q);   // nodes per chunk
-  const bool one_chunk = CH == Q; // the chunk holds every node: no re-evaluation
+  // the chunk holds every node: no re-evaluation (the single-chunk variant
+  // is launched only for Q <= NP)
+  const bool one_chunk = (PREC & 4) != 0 ? true : CH == Q;
   double* US = lamS + NP;         // [CH][M]
   double* JS = US + CH * M;       // [CH][NJ]
   double* cA = JS + CH * NJ;      // [2][NP] pivot column (LDS elimination)
@@ -489,7 +494,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           if (live[s])
             for (int j = 0; j < nq; ++j)
               gacc[s] = fma(US[j * M + aa[s]], wphiL[(c0 + j) * kp + ii[s]], gacc[s]);
-        wave_sync();
+        if (!one_chunk) wave_sync();
       }
       return okp;
     };
@@ -576,32 +581,33 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
           }
           // the nodes in the same ascending order; with several chunks the
           // ansatz of each chunk is evaluated again for the current dual
-          for (int c0 = 0; c0 < Q; c0 += CH) {
-            if (!one_chunk) {
+          auto node_term = [&](const int q, const double* Jq) {
+            double sb[R][M];
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+              const double wi = wphiL[q * kp + ii[s]] * live_f[s];
+#pragma unroll
+              for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
+            }
+            const_dptr ph = phiC + q * kg;  // uniform: scalar loads
+#pragma unroll
+            for (int c = 0; c < NP; ++c) {
+              const double v = ph[c / M];
+#pragma unroll
+              for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
+            }
+          };
+          if (one_chunk) {
+            for (int q = 0; q < Q; ++q) node_term(q, JS + q * NJ);
+          } else {
+            for (int c0 = 0; c0 < Q; c0 += CH) {
               double sdum = 0.0;
               (void)eval_nodes<M>(P, lamS, Nc, phiL, wphiL, kp, c0 + r, Q, US, JS, sdum, c0);
               wave_sync();
+              const int nq = Q - c0 < CH ? Q - c0 : CH;
+              for (int j = 0; j < nq; ++j) node_term(c0 + j, JS + j * NJ);
+              wave_sync();
             }
-            const int nq = Q - c0 < CH ? Q - c0 : CH;
-            for (int j = 0; j < nq; ++j) {
-              const int q = c0 + j;
-              const double* Jq = JS + j * NJ;
-              double sb[R][M];
-#pragma unroll
-              for (int s = 0; s < R; ++s) {
-                const double wi = wphiL[q * kp + ii[s]] * live_f[s];
-#pragma unroll
-                for (int b = 0; b < M; ++b) sb[s][b] = Jq[aidx[s][b]] * wi;
-              }
-              const_dptr ph = phiC + q * kg;  // uniform: scalar loads
-#pragma unroll
-              for (int c = 0; c < NP; ++c) {
-                const double v = ph[c / M];
-#pragma unroll
-                for (int s = 0; s < R; ++s) row[s][c] = fma(sb[s][c % M], v, row[s][c]);
-              }
-            }
-            if (!one_chunk) wave_sync();
           }
 #pragma unroll
           for (int s = 0; s < R; ++s)
@@ -973,7 +979,7 @@ __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) 
 // The inexact-Hessian variant keeps the whole inverse row live through the
 // sweep; for NP <= 32 it is held to the exact kernel's two wavefronts per SIMD.
 template <int M, int NP, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 3) == 2 && NP <= 32) ? 2 : 1)))
 void newton_kernel(DualParams P) {
   if (P.pend) {  // the handed-on cells, block by block
     const int cpb = (blockDim.x >> 6) * NewtonCfg<M, NP>::CPW;
@@ -1026,7 +1032,7 @@ __global__ __launch_bounds__(64) void batch_prefix_kernel(const DualParams* __re
 #endif
 
 template <int M, int NP, int PREC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == 2 && NP <= 32) ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((PREC & 3) == 2 && NP <= 32) ? 2 : 1)))
 void newton_batched(const DualParams* __restrict__ PP, const int* __restrict__ begin, int n) {
   const int k = batch_problem(begin, n, blockIdx.x);
   if (PP[k].pend) {

@@ -290,6 +290,13 @@ size_t big_lds_bytes(int M, int T, int Q, int kp, int prec = 0, bool bcache = tr
   return f(std::integral_constant<int, 4>{});
 }
 
+// Register-row kernel variant of a class: exact (0) and inexact-Hessian (2)
+// Newton take their single-chunk form (+4) when the cell's lanes hold every
+// node at once
+int reg_variant(int prec, int T, int NP, int Q) {
+  return (T == 0 && (prec == 0 || prec == 2) && Q <= NP) ? (prec | 4) : prec;
+}
+
 DualFn pick_dual(int M, int NP, int prec = 0) {
   if (M == 1) return dual_pick<1>(NP, prec);
   if (M == 3) return dual_pick<3>(NP, prec);
@@ -687,7 +694,7 @@ ipm_status launch_dual(ipm_ctx* ctx, const Problem& P, DualParams d, int c, bool
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     hipLaunchKernelGGL(fn, dim3(pend ? kPendBlocks : items), dim3(256), D.lds, ctx->stream, d);
   } else {
-    DualFn fn = pick_dual(P.M, D.NP, prec);
+    DualFn fn = pick_dual(P.M, D.NP, reg_variant(prec, 0, D.NP, P.Q));
     if (!fn) return fail(ctx, IPM_E_ARG, "no dual kernel for this size");
     const int per_block = D.waves * dual_cells_per_wave(P.M, D.NP);
     const int blocks = pend ? kPendBlocks : (items + per_block - 1) / per_block;
@@ -914,13 +921,14 @@ ipm_status plan_batch(ipm_ctx* ctx, const std::vector<int>& ids, BatchPlan& Bp,
         }
         const int per_block = D.T > 0 ? 1 : D.waves * dual_cells_per_wave(P.M, D.NP);
         const int threads = D.T > 0 ? 256 : 64 * D.waves;
+        const int kprec = reg_variant(D.prec, D.T, D.NP, P.Q);
         const std::string key = "1:" + std::to_string(P.M) + ":" + std::to_string(D.NP) + ":" +
                                 std::to_string(D.T) + ":" + std::to_string(threads) + ":" +
-                                std::to_string(D.prec) + (dc.pend ? ":p" : "");
+                                std::to_string(kprec) + (dc.pend ? ":p" : "");
         ng[key].push_back({dc, dc.pend ? kPendBlocks : (items + per_block - 1) / per_block, D.lds});
         nshape[key] = {threads, per_block};
-        nkind[key] = {P.M, D.NP, D.T > 0 ? 1 : 0, D.prec};
-        nfn[key] = pick_newton_batched(P.M, D.NP, D.T, D.prec);
+        nkind[key] = {P.M, D.NP, D.T > 0 ? 1 : 0, kprec};
+        nfn[key] = pick_newton_batched(P.M, D.NP, D.T, kprec);
         if (!nfn[key]) return fail(ctx, IPM_E_ARG, "no batched dual kernel for this size");
       }
       const std::string ukey = std::to_string(P.M) + ":" + std::to_string(P.UG) + ":" +
@@ -1180,7 +1188,7 @@ ipm_status set_kernel_attributes(ipm_ctx* ctx) {
   // raise the dynamic LDS limit above the 64 KiB default (best effort)
   for (int M : {1, 3, 4})
     for (int NP : {8, 16, 32, 64})
-      for (int prec : {0, 2, 10}) {
+      for (int prec : {0, 2, 4, 6, 10}) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(pick_dual(M, NP, prec)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, big);
         (void)hipFuncSetAttribute(pick_newton_batched(M, NP, 0, prec),
@@ -1690,6 +1698,9 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
                            hipMemcpyHostToDevice, s));
   }
   CHK(hipMemsetAsync(P.d_ctrl, 0, sizeof(StepCtrl), s));
+  // modes above a cell's fixed level stay zero in both moment buffers (the
+  // update writes only the cell's own modes; set-up fills buffer 0)
+  CHK(hipMemsetAsync(P.d_u[1], 0, cn * sizeof(double), s));
   if (P.d_hinv_ok) CHK(hipMemsetAsync(P.d_hinv_ok, 0, static_cast<size_t>(P.cells), s));
   std::vector<int> hslot;
   if (P.d_hinv_slot) {  // a cell's slot: its position in its class's cell order
@@ -2396,7 +2407,7 @@ ipm_status ipm_class_stats(ipm_ctx* ctx, int id, ipm_class_stat* out, int cap, i
     s.size_class = c;
     s.workgroup = D.T > 0 ? 1 : 0;
     s.lanes = D.NP;
-    s.variant = D.prec;
+    s.variant = reg_variant(D.prec, D.T, D.NP, P->Q);
     s.n_min = D.n_min;
     s.n_max = D.n_max;
     s.cells = D.count;

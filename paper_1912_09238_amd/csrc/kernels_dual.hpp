@@ -8,7 +8,7 @@
 namespace ipm {
 
 // prec 0: exact Newton; 2: inexact-Hessian (full kernel); 10: its chord
-// steps alone (chord.hpp)
+// steps alone (chord.hpp); 4 and 6: 0 and 2 for rules of at most NP nodes
 template <int M>
 DualFn dual_pick(int NP, int prec) {
   if (prec == 10) switch (NP) {
@@ -23,6 +23,21 @@ DualFn dual_pick(int NP, int prec) {
       case 32: return newton_kernel<M, 32, 2>;
       case 64: return newton_kernel<M, 64, 2>;
     }
+  if (prec == 4 || prec == 6) {
+    if (prec == 4) switch (NP) {
+        case 8: return newton_kernel<M, 8, 4>;
+        case 16: return newton_kernel<M, 16, 4>;
+        case 32: return newton_kernel<M, 32, 4>;
+        case 64: return newton_kernel<M, 64, 4>;
+      }
+    switch (NP) {
+      case 8: return newton_kernel<M, 8, 6>;
+      case 16: return newton_kernel<M, 16, 6>;
+      case 32: return newton_kernel<M, 32, 6>;
+      case 64: return newton_kernel<M, 64, 6>;
+    }
+    return nullptr;
+  }
   if (prec != 0) return nullptr;
   switch (NP) {
     case 8: return newton_kernel<M, 8>;
@@ -47,6 +62,21 @@ const void* dual_batched_pick(int NP, int prec) {
       case 32: return reinterpret_cast<const void*>(newton_batched<M, 32, 2>);
       case 64: return reinterpret_cast<const void*>(newton_batched<M, 64, 2>);
     }
+  if (prec == 4 || prec == 6) {
+    if (prec == 4) switch (NP) {
+        case 8: return reinterpret_cast<const void*>(newton_batched<M, 8, 4>);
+        case 16: return reinterpret_cast<const void*>(newton_batched<M, 16, 4>);
+        case 32: return reinterpret_cast<const void*>(newton_batched<M, 32, 4>);
+        case 64: return reinterpret_cast<const void*>(newton_batched<M, 64, 4>);
+      }
+    switch (NP) {
+      case 8: return reinterpret_cast<const void*>(newton_batched<M, 8, 6>);
+      case 16: return reinterpret_cast<const void*>(newton_batched<M, 16, 6>);
+      case 32: return reinterpret_cast<const void*>(newton_batched<M, 32, 6>);
+      case 64: return reinterpret_cast<const void*>(newton_batched<M, 64, 6>);
+    }
+    return nullptr;
+  }
   if (prec != 0) return nullptr;
   switch (NP) {
     case 8: return reinterpret_cast<const void*>(newton_batched<M, 8>);

@@ -184,9 +184,15 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
   const int cell = blk * groups + gid;
   // operands that do not depend on the time step are requested before the
   // step's speed reduction, so the two memory round trips overlap: this
-  // lane's first node of the cell and of its neighbours, its first old moment
+  // lane's first node of the cell and of its neighbours, and the old moments
+  // that this lane's projection replaces first
   const double *uc = nullptr, *uw = nullptr, *ue = nullptr, *us = nullptr, *un = nullptr;
-  double pc[M], pw[M], pe[M], ps[M], pn[M], uold0 = 0.0;
+  // small cells on few nodes project one moment (variable, mode) per lane
+  // over all nodes: one load and one store per lane instead of M of each
+  const bool direct = M * N <= G && Q <= 32;
+  double pc[M], pw[M], pe[M], ps[M], pn[M], uoldp[M];
+#pragma unroll
+  for (int b = 0; b < M; ++b) uoldp[b] = 0.0;
   if (cell < P.cells) {
     const int ix = cell % P.nx, iy = cell / P.nx;
     uc = P.nodal + static_cast<size_t>(cell) * Q * M;
@@ -204,7 +210,12 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         pn[b] = un[r * M + b];
       }
     }
-    if (r < M * N) uold0 = P.uold[static_cast<size_t>(cell) * M * N + r];
+    if (direct) {  // this lane's one moment
+      if (r < M * N) uoldp[0] = P.uold[static_cast<size_t>(cell) * M * N + r];
+    } else if (r < N) {
+#pragma unroll
+      for (int b = 0; b < M; ++b) uoldp[b] = P.uold[static_cast<size_t>(cell) * M * N + static_cast<size_t>(b) * N + r];
+    }
   }
   if (stop_done || stop_status) {  // uniform: the block leaves before any barrier
     if (blk == 0 && threadIdx.x == 0) {
@@ -362,13 +373,35 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
           v = lc[i] - dt / P.dx * (gr - gl);
         }
         const size_t off = static_cast<size_t>(cell) * M * N + k;
-        const double d = v - (k == r ? uold0 : P.uold[off]);
+        const double d = v - ((M == 1 && k == r) ? uoldp[0] : P.uold[off]);
         d2 = fma(d, d, d2);
         finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
         P.unew[off] = v;
         const double g = h - v;  // next step's dual gradient at its warm start
 #pragma unroll
         for (int bb = 0; bb < M; ++bb) gsq[bb] += (bb == b) ? g * g : 0.0;
+      }
+    } else if (direct) {
+      // lane r: moment k = r of the cell (variable k / N, mode k mod N)
+      for (int k = r; k < M * N; k += G) {
+        const int b = k / N, i = k % N;
+        double v = 0.0, h = 0.0;
+        if (i < Nn)
+          for (int q = 0; q < Q; ++q) {
+            const double w = wphiL[q * kp + i];
+            v = fma(ut[q * M + b], w, v);
+            h = fma(uq[q * M + b], w, h);
+          }
+        const size_t off = static_cast<size_t>(cell) * M * N + k;
+        const double d = v - (k == r ? uoldp[0] : P.uold[off]);
+        d2 = fma(d, d, d2);
+        finite &= (v == v && fabs(v) < 1e300) ? 1 : 0;
+        P.unew[off] = v;
+        const double g = h - v;  // next step's dual gradient at its warm start
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) gsq[bb] += (bb == b) ? g * g : 0.0;
+        if (P.gwarm && i < Nn) P.uold[off] = g;
+        if (P.gwarm && k == 0) P.s0[cell] = (P.gamma - 1.0) * h;
       }
     } else {
       // projection on the Nn modes of the cell's level: lane r takes mode
@@ -417,7 +450,8 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
 #pragma unroll
           for (int b = 0; b < M; ++b) {
             const size_t off = static_cast<size_t>(cell) * M * N + static_cast<size_t>(b) * N + i;
-            const double d = v[b] - P.uold[off];
+            // the first round's storing lanes hold mode i = r: prefetched
+            const double d = v[b] - (t == 0 ? uoldp[b] : P.uold[off]);
             d2 = fma(d, d, d2);
             finite &= (v[b] == v[b] && fabs(v[b]) < 1e300) ? 1 : 0;
             P.unew[off] = v[b];
@@ -431,8 +465,9 @@ __device__ __forceinline__ void update_body(const UpdateParams& P, const int blk
         }
       }
       // modes above the level: zero (a lowered cell's old moments there
-      // enter the residual)
-      const int nz = N - Nn;
+      // enter the residual).  Without adaptivity a cell's level is fixed
+      // and both moment buffers hold zeros there from set-up on.
+      const int nz = P.adapt ? N - Nn : 0;
       for (int k = r; k < M * nz; k += G) {
         const size_t off = static_cast<size_t>(cell) * M * N + static_cast<size_t>(k / nz) * N + Nn + k % nz;
         const double d = P.uold[off];
