@@ -1113,7 +1113,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
-                     "kernel": "newton_kernel<3,32,0>", "dual_us_avg": dual_avg_s * 1e6,
+                     "kernel": "newton_kernel<3,32,4>", "dual_us_avg": dual_avg_s * 1e6,
                      "update_us_avg": upd_avg_s * 1e6,
                      "flops_per_launch": flops_per_launch},
         "kbar": newton / cell_updates,

@@ -380,16 +380,16 @@ __device__ __forceinline__ int work_cell(const DualParams& P, int item) {
   return item < P.cells ? item : -1;
 }
 
-__device__ __forceinline__ void reset_next_step(const DualParams& P) {
-  StepCtrl* C = P.ctrl;
+__device__ __forceinline__ void reset_next_ctrl(StepCtrl* C, int parity) {
   for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
-    C->amax[P.parity ^ 1][0][k * kSlotStride] = 0ull;
-    C->amax[P.parity ^ 1][1][k * kSlotStride] = 0ull;
+    C->amax[parity ^ 1][0][k * kSlotStride] = 0ull;
+    C->amax[parity ^ 1][1][k * kSlotStride] = 0ull;
   }
   for (int k = threadIdx.x; k < kCls * kSlots; k += blockDim.x)
-    C->list_len[list_len_index(P.parity ^ 1, k / kSlots, k % kSlots)] = 0u;
-  for (int k = threadIdx.x; k < kCls; k += blockDim.x) C->pend_len[P.parity ^ 1][k] = 0u;
+    C->list_len[list_len_index(parity ^ 1, k / kSlots, k % kSlots)] = 0u;
+  for (int k = threadIdx.x; k < kCls; k += blockDim.x) C->pend_len[parity ^ 1][k] = 0u;
 }
+__device__ __forceinline__ void reset_next_step(const DualParams& P) { reset_next_ctrl(P.ctrl, P.parity); }
 
 template <int M, int NP, int PREC = 0>
 __device__ __forceinline__ void newton_body(const DualParams& P, const int blk) {
@@ -1010,23 +1010,45 @@ __device__ __forceinline__ int batch_problem(const int* __restrict__ begin, int 
 // begin[k] on, so all listed cells sit in the first blocks of the grid.  It
 // also clears each problem's next-step lists and speed slots (the duty of
 // the problem's first Newton launch of the step, flagged reset_next).  One
-// wavefront.
+// wavefront; lane j takes problem k0 + j of each group of 64 (its flags and
+// list lengths are independent loads), the block counts are scanned across
+// the lanes, and the resets run problem by problem on all lanes.
 __global__ __launch_bounds__(64) void batch_prefix_kernel(const DualParams* __restrict__ PP, int n,
                                                           int per_block, int* __restrict__ begin) {
   const int lane = threadIdx.x;
   int acc = 0;
   if (lane == 0) begin[0] = 0;
-  for (int k = 0; k < n; ++k) {
-    const DualParams& P = PP[k];
-    int listed = 0;
-    if (!(P.ctrl->done[P.parity] || P.ctrl->status)) {
-      const int v = min(static_cast<int>(P.ctrl->list_len[list_len_index(P.parity, P.cls, lane)]),
-                        P.list_cap);
-      listed = static_cast<int>(wave_sum(static_cast<double>(v)));
-      if (P.reset_next) reset_next_step(P);
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    const int k = k0 + lane;
+    int blocks = 0, reset = 0, parity = 0;
+    StepCtrl* C = nullptr;
+    if (k < n) {
+      const DualParams& P = PP[k];
+      C = P.ctrl;
+      parity = P.parity;
+      if (!(C->done[parity] || C->status)) {
+        const unsigned* len = C->list_len + list_len_index(parity, P.cls, 0);
+        int listed = 0;
+        for (int s = 0; s < kSlots; ++s) listed += min(static_cast<int>(len[s * kSlotStride]), P.list_cap);
+        blocks = (listed + per_block - 1) / per_block;
+        reset = P.reset_next;
+      }
     }
-    acc += (listed + per_block - 1) / per_block;
-    if (lane == 0) begin[k + 1] = acc;
+    int v = blocks;  // inclusive scan over the group's problems
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (k < n) begin[k + 1] = acc + v;
+    acc += __shfl(v, 63, 64);
+    unsigned long long todo = __ballot(reset != 0);
+    while (todo != 0ull) {
+      const int j = __ffsll(static_cast<long long>(todo)) - 1;
+      todo &= todo - 1ull;
+      StepCtrl* Cj = reinterpret_cast<StepCtrl*>(
+          __shfl(static_cast<long long>(reinterpret_cast<uintptr_t>(C)), j, 64));
+      reset_next_ctrl(Cj, __shfl(parity, j, 64));
+    }
   }
 }
 #endif
