@@ -27,6 +27,7 @@ enum : unsigned {
 
 struct ClosureParams {
   int entropy;
+  int g75;  // gamma = 7/5: the Euler closure's power of beta in closed form
   double gamma, um, up;
   double log_range;  // ln(u_plus - u_minus), log-barrier constant of s_*
   double r1mg;       // 1 / (1 - gamma): the Euler closure multiplies by it
@@ -106,8 +107,11 @@ __device__ __forceinline__ bool closure(const ClosureParams& cp, const double* L
       v[k] = L[1 + k] * ib;
       vv += v[k] * v[k];
     }
-    const double lnrho = (log(beta) - 0.5 * beta * vv + cp.gamma - L[0]) * cp.r1mg;
-    const double rho = exp(lnrho);
+    // rho = beta^(1/(1-gamma)) exp((gamma - L_rho - |L_m|^2/(2 beta)) / (1-gamma));
+    // for gamma = 7/5 the power is beta^(-5/2) = ib^2 sqrt(ib): a square
+    // root instead of a logarithm
+    const double rho = cp.g75 ? exp((cp.gamma - L[0] - 0.5 * beta * vv) * cp.r1mg) * (ib * ib * sqrt(ib))
+                              : exp((log(beta) - 0.5 * beta * vv + cp.gamma - L[0]) * cp.r1mg);
     const double h = 0.5 * vv + ib;
     u[0] = rho;
 #pragma unroll

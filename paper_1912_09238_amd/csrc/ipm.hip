@@ -1530,6 +1530,7 @@ ipm_status ipm_set_problem(ipm_ctx* ctx, const ipm_problem* pb, int* problem_id)
   P.cp.entropy = pb->entropy;
   P.cp.gamma = pb->gamma;
   P.cp.r1mg = 1.0 / (1.0 - pb->gamma);
+  P.cp.g75 = pb->gamma == 1.4 ? 1 : 0;
   P.cp.um = pb->u_minus;
   P.cp.up = pb->u_plus;
   P.cp.log_range = pb->entropy == IPM_ENT_LOG_BARRIER ? std::log(pb->u_plus - pb->u_minus) : 0.0;
