@@ -322,8 +322,10 @@ ipm_status ipm_autotune(ipm_ctx *ctx, int n_ids, const int *ids, int steps_per_c
 /* Wait for the context's stream and fill *info for one problem. */
 ipm_status ipm_query(ipm_ctx *ctx, int id, ipm_step_info *info);
 
-/* Current moments [cells][m][N] of a problem (modes above a cell's degree are
-   zero).  out_is_device: out is a device pointer (copy ordered on the
+/* Current moments [cells][m][N] of a problem: the stochastic-Galerkin moments
+   uhat_i = <u phi_i> of the state on the gPC basis (Sec. 2, the moment
+   system that eq:momentIterationFunction advances); modes above a cell's
+   degree are zero.  out_is_device: out is a device pointer (copy ordered on the
    context stream, asynchronous) or a host pointer (synchronous).
    out_len = capacity of out in doubles. */
 ipm_status ipm_moments(ipm_ctx *ctx, int id, double *out, size_t out_len, int out_is_device);

@@ -161,6 +161,7 @@ struct BatchPlan {
   int* d_begin = nullptr;
   int* d_dev_begin = nullptr;  // device-computed block offsets of list-mode Newton launches
   size_t nd = 0, nu = 0;
+  size_t cap_dp = 0, cap_up = 0, cap_begin = 0;  // element capacities of the owned arrays
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   bool owned = true;  // false: the arrays live in the static scratch (not freed)
@@ -221,6 +222,11 @@ struct ipm_ctx {
   std::vector<ipm_launch_time> ltimes;  // totals of the last timing window
   unsigned long long gen = 0;              // bumped when problems or launch shapes change
   std::unique_ptr<BatchPlan> batch;        // cached plan of the last batched ipm_step
+  // serving loop's poll: the control-block heads of the active problems
+  // gathered on the device, one copy into pinned host memory per round
+  unsigned long long* d_poll = nullptr;
+  unsigned long long* h_poll = nullptr;
+  size_t poll_cap = 0;  // problems
   std::map<std::string, int> tuned_waves;  // autotuner: wavefronts per Newton block by shape
   // ipm_step_static: this device's scratch address, the plan it stepped last
   // and the host copies of that plan's arrays
@@ -1005,23 +1011,48 @@ ipm_status add_graphs(ipm_ctx* ctx, BatchPlan& Bp);
 // graphs are added when the same plan is stepped a second time (add_graphs):
 // a plan that changes every call (a serving loop admitting and finishing
 // requests) runs launch by launch instead of paying two instantiations.
-ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out) {
+// prev (nullable): a retired plan of this context, idle on the device; its
+// parameter arrays are taken over where they are large enough, so that a
+// serving loop whose batch changes every round does not allocate and free
+// (hipFree waits for the whole device) on every change.
+ipm_status build_batch(ipm_ctx* ctx, const std::vector<int>& ids, std::unique_ptr<BatchPlan>& out,
+                       BatchPlan* prev = nullptr) {
   auto B = std::make_unique<BatchPlan>();
   std::vector<DualParams> dps;
   std::vector<UpdateParams> ups;
   std::vector<int> begins;
   ipm_status pst = plan_batch(ctx, ids, *B, dps, ups, begins);
   if (pst != IPM_OK) return pst;
-  HIPCHK(ctx, hipMalloc(&B->d_dp, std::max<size_t>(dps.size(), 1) * sizeof(DualParams)));
-  HIPCHK(ctx, hipMalloc(&B->d_up, std::max<size_t>(ups.size(), 1) * sizeof(UpdateParams)));
-  HIPCHK(ctx, hipMalloc(&B->d_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
+  if (prev && !prev->owned) prev = nullptr;
+  auto take = [&](auto*& mine, auto*& theirs, size_t& cap, size_t theirs_cap, size_t need) {
+    using T = std::remove_reference_t<decltype(*mine)>;
+    need = std::max<size_t>(need, 1);
+    if (prev && theirs && theirs_cap >= need) {
+      mine = theirs;
+      theirs = nullptr;
+      cap = theirs_cap;
+      return hipSuccess;
+    }
+    cap = need;
+    return hipMalloc(reinterpret_cast<void**>(&mine), need * sizeof(T));
+  };
+  {
+    size_t cap_b2 = 0;
+    BatchPlan none;
+    BatchPlan& pv = prev ? *prev : none;
+    HIPCHK(ctx, take(B->d_dp, pv.d_dp, B->cap_dp, pv.cap_dp, dps.size()));
+    HIPCHK(ctx, take(B->d_up, pv.d_up, B->cap_up, pv.cap_up, ups.size()));
+    HIPCHK(ctx, take(B->d_begin, pv.d_begin, B->cap_begin, pv.cap_begin, begins.size()));
+    HIPCHK(ctx, take(B->d_dev_begin, pv.d_dev_begin, cap_b2, pv.cap_begin, begins.size()));
+    // both block-offset arrays hold cap_begin entries
+    if (cap_b2 < B->cap_begin) B->cap_begin = cap_b2;
+  }
   HIPCHK(ctx, hipMemcpyAsync(B->d_dp, dps.data(), dps.size() * sizeof(DualParams),
                              hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(B->d_up, ups.data(), ups.size() * sizeof(UpdateParams),
                              hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(B->d_begin, begins.data(), begins.size() * sizeof(int),
                              hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(ctx, hipMalloc(&B->d_dev_begin, std::max<size_t>(begins.size(), 1) * sizeof(int)));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   out = std::move(B);
   return IPM_OK;
@@ -1322,6 +1353,21 @@ static_assert(offsetof(CtrlFlags, done) == offsetof(StepCtrl, done) &&
                   offsetof(CtrlFlags, steps) == offsetof(StepCtrl, steps),
               "CtrlFlags mirrors the head of StepCtrl");
 
+// The serving loop's poll: the CtrlFlags heads of up to kPollBatch problems
+// gathered into one contiguous device array (one 64-bit word per thread), so
+// that a single device-to-host copy returns the flags of every active problem.
+constexpr int kPollBatch = 64;
+constexpr int kFlagWords = static_cast<int>(sizeof(CtrlFlags) / sizeof(unsigned long long));
+static_assert(sizeof(CtrlFlags) % sizeof(unsigned long long) == 0, "CtrlFlags is whole words");
+struct PollSources {
+  const unsigned long long* src[kPollBatch];
+};
+__global__ __launch_bounds__(kPollBatch* kFlagWords) void poll_gather_kernel(PollSources ps, int n,
+                                                                             unsigned long long* dst) {
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < n * kFlagWords) dst[t] = ps.src[t / kFlagWords][t % kFlagWords];
+}
+
 // Device temporaries of one call: freed when the call returns, on every
 // path, once the stream has drained.
 struct TempBuffers {
@@ -1492,6 +1538,8 @@ ipm_status ipm_destroy(ipm_ctx* ctx) {
   for (auto& p : ctx->problems) free_problem(p.get());
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->lev) (void)hipEventDestroy(e);
+  if (ctx->d_poll) (void)hipFree(ctx->d_poll);
+  if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return IPM_OK;
@@ -1914,8 +1962,8 @@ ipm_status ipm_step(ipm_ctx* ctx, int n_ids, const int* ids, int max_steps, ipm_
     if (!batch_valid(ctx, ctx->batch.get(), v)) {
       // the old plan's graphs may still be queued: drain before freeing
       if (ctx->batch) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-      ctx->batch.reset();
-      ipm_status st = build_batch(ctx, v, ctx->batch);
+      std::unique_ptr<BatchPlan> retired = std::move(ctx->batch);
+      ipm_status st = build_batch(ctx, v, ctx->batch, retired.get());
       if (st != IPM_OK) return st;
     } else if (!ctx->batch->exec[0]) {
       ipm_status st = add_graphs(ctx, *ctx->batch);  // the plan is stepped again: replay it
@@ -2119,8 +2167,9 @@ ipm_status ipm_release(ipm_ctx* ctx, int id) {
   if (!P) return fail(ctx, IPM_E_STATE, "ipm_release: unknown problem id");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->used -= std::min(ctx->used, P->charged);
+  // the cached plan goes stale with the generation (it is never launched
+  // again); it stays only so that the next plan can take over its arrays
   ++ctx->gen;
-  ctx->batch.reset();
   free_problem(P);
   ctx->problems[id].reset();
   return IPM_OK;
@@ -2147,8 +2196,8 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
   int finished = 0;
   std::vector<int> active_req, active_id;
   std::vector<CtrlFlags> ctrl;
-  while (finished < n) {
-    // admission, in arrival order, while slots and HBM budget allow
+  // admission, in arrival order, while slots and HBM budget allow
+  auto admit = [&]() -> ipm_status {
     while (next < order.size() && reqs[order[next]].arrival_s <= now_s() &&
            static_cast<int>(active_req.size()) < max_active) {
       ipm_request& R = reqs[order[next]];
@@ -2167,6 +2216,11 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
       active_req.push_back(order[next - 1]);
       active_id.push_back(pid);
     }
+    return IPM_OK;
+  };
+  while (finished < n) {
+    ipm_status st = admit();
+    if (st != IPM_OK) return st;
     if (active_req.empty()) {
       if (next < order.size()) {
         const double wait = reqs[order[next]].arrival_s - now_s();
@@ -2174,16 +2228,40 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
       }
       continue;
     }
-    // one round of batched steps, then the stop flags of all active problems
-    ipm_status st = ipm_step(ctx, static_cast<int>(active_id.size()), active_id.data(),
-                             steps_per_round, nullptr);
+    // one round of batched steps for the problems active now; while it runs,
+    // the host prepares the requests that arrived meanwhile (their set-up
+    // work queues behind the round on the stream), then the stop flags of
+    // the problems the round stepped
+    const size_t na = active_id.size();
+    st = ipm_step(ctx, static_cast<int>(na), active_id.data(), steps_per_round, nullptr);
     if (st != IPM_OK) return st;
-    ctrl.resize(active_id.size());
-    for (size_t k = 0; k < active_id.size(); ++k)
-      HIPCHK(ctx, hipMemcpyAsync(&ctrl[k], get(ctx, active_id[k])->d_ctrl, sizeof(CtrlFlags),
-                                 hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = admit()) != IPM_OK) return st;
+    ctrl.resize(na);
+    if (ctx->poll_cap < na) {
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      if (ctx->d_poll) (void)hipFree(ctx->d_poll);
+      if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
+      ctx->d_poll = ctx->h_poll = nullptr;
+      ctx->poll_cap = 0;
+      const size_t cap = (na + kPollBatch - 1) / kPollBatch * kPollBatch;
+      HIPCHK(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_poll), cap * sizeof(CtrlFlags)));
+      HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->h_poll), cap * sizeof(CtrlFlags)));
+      ctx->poll_cap = cap;
+    }
+    for (size_t k0 = 0; k0 < na; k0 += kPollBatch) {
+      PollSources ps{};
+      const int nb = static_cast<int>(std::min<size_t>(kPollBatch, na - k0));
+      for (int j = 0; j < nb; ++j)
+        ps.src[j] = reinterpret_cast<const unsigned long long*>(get(ctx, active_id[k0 + j])->d_ctrl);
+      hipLaunchKernelGGL(poll_gather_kernel, dim3(1), dim3(kPollBatch * kFlagWords), 0, ctx->stream,
+                         ps, nb, ctx->d_poll + k0 * kFlagWords);
+      HIPCHK(ctx, hipGetLastError());
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_poll, ctx->d_poll, na * sizeof(CtrlFlags),
+                               hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (size_t k = 0; k < active_id.size();) {
+    std::memcpy(ctrl.data(), ctx->h_poll, na * sizeof(CtrlFlags));
+    for (size_t k = 0, polled = na; k < polled;) {
       const CtrlFlags& hc = ctrl[k];
       const bool done = hc.done[hc.steps & 1] || hc.status;
       if (!done) {
@@ -2207,6 +2285,7 @@ ipm_status ipm_serve(ipm_ctx* ctx, int n, ipm_request* reqs, int steps_per_round
       active_req.erase(active_req.begin() + static_cast<long>(k));
       active_id.erase(active_id.begin() + static_cast<long>(k));
       ctrl.erase(ctrl.begin() + static_cast<long>(k));
+      --polled;
     }
   }
   return IPM_OK;
