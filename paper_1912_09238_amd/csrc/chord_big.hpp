@@ -45,6 +45,12 @@ struct ChordBigCfg {
   }
 };
 
+// three wavefronts per SIMD (168 registers) where LDS allows three
+// workgroups per CU (up to T = 6 at 125 nodes); no request above (their LDS
+// allows two, and a two-wave cap cost the 144-row class 9 % of its time)
+template <int T>
+constexpr int chord_big_waves() { return T <= 6 ? 3 : 1; }
+
 // sum over the workgroup kernel's 256 threads, thread 64 s + lane in slot s
 // (the four slots of a lane first: one wavefront sum instead of four)
 __device__ __forceinline__ double sum4(const double (&x)[4]) {
@@ -226,33 +232,77 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       double gc[T];
 #pragma unroll
       for (int j = 0; j < T; ++j) gc[j] = gS[tc + 16 * j];
-      // all 256 tile threads (tile rows tr = 0..15 at every T)
+      // all 256 tile threads (tile rows tr = 0..15 at every T).  When the
+      // ansatz area (free until the next pass over the nodes) holds them,
+      // the row sums of IB tiles are formed with all their loads in flight
+      // and staged there (rows of 16 at a stride of 17 doubles: the reads
+      // below hit distinct banks); one lane per (tile, row) then adds the
+      // 16 column sums in ascending order, the order of the broadcast chain
+      // of the other path, so both give the same bits.  Only for the tiles
+      // above the three-wavefront register budget (T > 6): within it the
+      // staged form spills (measured slower at T = 5).
+      constexpr int IB = T < 4 ? T : 4;
+      constexpr bool staged = chord_big_waves<T>() != 3;
+      if (staged && Q * M >= 68 * IB) {  // uniform
+        const int rr0 = lane >> 4;
 #pragma unroll 1
-      for (int s = 0; s < 4; ++s) {
-        const int u = 64 * s + lane, tr = u >> 4;
-#pragma unroll 1
-        for (int i = 0; i < T; ++i) {
-          double ps = 0.0;
+        for (int s = 0; s < 4; ++s) {
+          const int u = 64 * s + lane;
 #pragma unroll
-          for (int j = 0; j < T; ++j) ps = fma(static_cast<double>(Hc[(i * T + j) * 256 + u]), gc[j], ps);
-          double dv = 0.0;
-          dv += row_bcast<0>(ps);
-          dv += row_bcast<1>(ps);
-          dv += row_bcast<2>(ps);
-          dv += row_bcast<3>(ps);
-          dv += row_bcast<4>(ps);
-          dv += row_bcast<5>(ps);
-          dv += row_bcast<6>(ps);
-          dv += row_bcast<7>(ps);
-          dv += row_bcast<8>(ps);
-          dv += row_bcast<9>(ps);
-          dv += row_bcast<10>(ps);
-          dv += row_bcast<11>(ps);
-          dv += row_bcast<12>(ps);
-          dv += row_bcast<13>(ps);
-          dv += row_bcast<14>(ps);
-          dv += row_bcast<15>(ps);
-          if (tc == 0) dS[tr + 16 * i] = dv;
+          for (int i0 = 0; i0 < T; i0 += IB) {
+#pragma unroll
+            for (int k = 0; k < IB; ++k) {
+              const int i = i0 + k;
+              if (i < T) {
+                double ps = 0.0;
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                  ps = fma(static_cast<double>(Hc[(i * T + j) * 256 + u]), gc[j], ps);
+                US[k * 68 + rr0 * 17 + tc] = ps;
+              }
+            }
+            wave_sync();
+            if (lane < 4 * IB) {
+              const int k = lane >> 2, rr = lane & 3;
+              if (i0 + k < T) {
+                const double* pp = US + k * 68 + rr * 17;
+                double dv = 0.0;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) dv += pp[c];
+                dS[4 * s + rr + 16 * (i0 + k)] = dv;
+              }
+            }
+            wave_sync();
+          }
+        }
+      } else {
+#pragma unroll 1
+        for (int s = 0; s < 4; ++s) {
+          const int u = 64 * s + lane, tr = u >> 4;
+#pragma unroll 1
+          for (int i = 0; i < T; ++i) {
+            double ps = 0.0;
+#pragma unroll
+            for (int j = 0; j < T; ++j) ps = fma(static_cast<double>(Hc[(i * T + j) * 256 + u]), gc[j], ps);
+            double dv = 0.0;
+            dv += row_bcast<0>(ps);
+            dv += row_bcast<1>(ps);
+            dv += row_bcast<2>(ps);
+            dv += row_bcast<3>(ps);
+            dv += row_bcast<4>(ps);
+            dv += row_bcast<5>(ps);
+            dv += row_bcast<6>(ps);
+            dv += row_bcast<7>(ps);
+            dv += row_bcast<8>(ps);
+            dv += row_bcast<9>(ps);
+            dv += row_bcast<10>(ps);
+            dv += row_bcast<11>(ps);
+            dv += row_bcast<12>(ps);
+            dv += row_bcast<13>(ps);
+            dv += row_bcast<14>(ps);
+            dv += row_bcast<15>(ps);
+            if (tc == 0) dS[tr + 16 * i] = dv;
+          }
         }
       }
       wave_sync();
@@ -426,12 +476,6 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
     if (P.dim == 2) atomicMax(&P.ctrl->amax[P.parity][1][slot], speed_bits(my));
   }
 }
-
-// three wavefronts per SIMD (168 registers) where LDS allows three
-// workgroups per CU (up to T = 6 at 125 nodes); no request above (their LDS
-// allows two, and a two-wave cap cost the 144-row class 9 % of its time)
-template <int T>
-constexpr int chord_big_waves() { return T <= 6 ? 3 : 1; }
 
 template <int M, int T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(chord_big_waves<T>())))
