@@ -46,10 +46,15 @@ struct ChordBigCfg {
 };
 
 // three wavefronts per SIMD (168 registers) where LDS allows three
-// workgroups per CU (up to T = 6 at 125 nodes); no request above (their LDS
-// allows two, and a two-wave cap cost the 144-row class 9 % of its time)
+// workgroups per CU (up to T = 6 at 125 nodes), except at T = 5; no request
+// there and above (their LDS allows two, and a two-wave cap cost the 144-row
+// class 9 % of its time).  T = 5 (the 80-row class of the 125-node batch)
+// trades the third wavefront for the staged row sums of the product with
+// the stored tiles, which do not fit 168 registers (chord launch 7.69 ->
+// 7.01 ms); T = 6 keeps three (the 84-row class of the 64-node bump, whose
+// ansatz area cannot stage four tiles, ran 19 % slower with two)
 template <int T>
-constexpr int chord_big_waves() { return T <= 6 ? 3 : 1; }
+constexpr int chord_big_waves() { return (T <= 4 || T == 6) ? 3 : 1; }
 
 // sum over the workgroup kernel's 256 threads, thread 64 s + lane in slot s
 // (the four slots of a lane first: one wavefront sum instead of four)
@@ -239,8 +244,8 @@ __device__ __forceinline__ void chord_big_body(const DualParams& P, const int bl
       // below hit distinct banks); one lane per (tile, row) then adds the
       // 16 column sums in ascending order, the order of the broadcast chain
       // of the other path, so both give the same bits.  Only for the tiles
-      // above the three-wavefront register budget (T > 6): within it the
-      // staged form spills (measured slower at T = 5).
+      // outside the three-wavefront register budget: within it the staged
+      // form spills (measured 49 % slower at T = 5).
       constexpr int IB = T < 4 ? T : 4;
       constexpr bool staged = chord_big_waves<T>() != 3;
       if (staged && Q * M >= 68 * IB) {  // uniform
