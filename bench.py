@@ -967,6 +967,11 @@ def main():
         args.warmup = 5 if args.warmup is None else args.warmup
         print(json.dumps(headline_form(args)), flush=True)
         return
+    if args.form == "batch":
+        # --steps / --warmup, when given, are the batch form's timed and
+        # untimed steps (else --batch-steps / --batch-warmup)
+        args.batch_steps = args.batch_steps if args.steps is None else args.steps
+        args.batch_warmup = args.batch_warmup if args.warmup is None else args.warmup
     args.steps = 5000 if args.steps is None else args.steps
     args.warmup = 20 if args.warmup is None else args.warmup
     if args.form == "batch":
