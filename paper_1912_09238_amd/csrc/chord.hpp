@@ -38,8 +38,14 @@ struct ChordCfg {
   // nodes per chunk: one per lane, as the full kernel (the same lanes sum
   // the same nodes, so both kernels round alike)
   __host__ __device__ static int chunk(int Q) { return Q < G ? Q : G; }
-  // per group: dual [NP], ansatz [CH][M]
-  __host__ __device__ static int group_doubles(int Q) { return NP + chunk(Q) * M; }
+  // one cell per wavefront and at most two chunks: the ansatz of every node
+  // stays in LDS after a pass (the write-back of the final dual's nodal
+  // ansatz reads it instead of evaluating the closure again)
+  __host__ __device__ static bool keep_all(int Q) { return CPW == 1 && Q <= 2 * G; }
+  // per group: dual [NP], ansatz [CH][M] (keep_all: [Q][M])
+  __host__ __device__ static int group_doubles(int Q) {
+    return NP + (keep_all(Q) ? Q : chunk(Q)) * M;
+  }
   // node stride of the tables, which are stored mode by mode (a node per
   // lane reads consecutive words); odd, so that lanes of different modes
   // read different banks
@@ -160,7 +166,8 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
   const int CH = Cfg::chunk(Q);
   double* areas = wL + Q;
   double* lamS = areas + static_cast<size_t>(wave * CPW + grp) * Cfg::group_doubles(Q);  // [NP]
-  double* US = lamS + NP;                                                                // [CH][M]
+  double* US = lamS + NP;  // [CH][M], keep_all: [Q][M]
+  const bool keep = Cfg::keep_all(Q);
   double* stats = areas + static_cast<size_t>(waves) * CPW * Cfg::group_doubles(Q);
   __syncthreads();
 
@@ -189,7 +196,7 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
           double u[M], ss;
           okp &= node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss) ? 1 : 0;
 #pragma unroll
-          for (int a = 0; a < M; ++a) US[r * M + a] = u[a];
+          for (int a = 0; a < M; ++a) US[(keep ? q : r) * M + a] = u[a];
           ssum = fma(wL[q], ss, ssum);
         }
         wave_sync();
@@ -198,7 +205,8 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
         // wL holds w_q exactly and the terms equal wL[q] * phi_i(q))
         if (live) {
           const double* wr = wphiT + ii * QT + c0;
-          for (int j = 0; j < nq; ++j) gacc = fma(US[j * M + aa], wr[j], gacc);
+          const double* uc = keep ? US + c0 * M : US;
+          for (int j = 0; j < nq; ++j) gacc = fma(uc[j * M + aa], wr[j], gacc);
         }
         wave_sync();
       }
@@ -369,9 +377,18 @@ __device__ __forceinline__ void chord_body(const DualParams& P, const int blk) {
     if (pending || status) {
       if (r == 0 && pending) hand_on(P, cell);
     } else {
+      // keep_all and a pass made: the last pass was at the final dual (the
+      // accepted trial, or the entry pass of a cell already within tau), and
+      // its nodal ansatz is in LDS, the same values bit for bit
+      const bool stored = keep && evals > 0;
       for (int q = r; q < Q; q += G) {
         double u[M], ss;
-        (void)node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss);
+        if (stored) {
+#pragma unroll
+          for (int b = 0; b < M; ++b) u[b] = US[q * M + b];
+        } else {
+          (void)node_ansatz<M>(P, lamS, Nc, phiT + q, QT, u, ss);
+        }
 #pragma unroll
         for (int b = 0; b < M; ++b) P.nodal[(static_cast<size_t>(cell) * Q + q) * M + b] = u[b];
         double ax, ay;
