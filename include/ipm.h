@@ -300,8 +300,11 @@ ipm_status ipm_select_degrees(int p, int max_degree, int quad_per_dim, int m, in
    admission signal; a request that cannot fit even alone fails with it).
    Admitted requests keep their moment and dual state resident and advance
    together, steps_per_round batched time steps per round (ipm_step with all
-   active ids); new requests join at round boundaries and finished ones leave
-   (moments copied to moments_out, state released).  Every request's result
+   active ids); requests that arrive while a round runs are set up meanwhile
+   (their set-up work queues behind the round on the context's stream) and
+   join the next round; finished ones leave at round boundaries (moments
+   copied to moments_out, state released).  The stop flags of the active
+   problems come back in one copy per round.  Every request's result
    equals that of stepping it alone.  Blocks until every request finished or
    failed; per-request failures are reported in reqs[k].status, the return
    value only reports device or argument errors. */
